@@ -1,0 +1,88 @@
+"""Stationary covariance kernels kappa(r) and their parameter derivatives (FP64).
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
+
+Sec. 2.1 works with a stationary, decaying kernel K = kappa(|x - x'|).  The
+paper does not fix its form; the benchmark workloads name three, written here
+with amplitude sigma (variance sigma^2), length scale ell and an absolute
+nugget tau added only where the two arguments are the same point (same index):
+
+* EXP: sigma^2 exp(-r/ell)                      (Matern nu = 1/2)
+* M32: sigma^2 (1 + a) exp(-a),  a = sqrt(3) r/ell   (Matern nu = 3/2)
+* SE : sigma^2 exp(-r^2 / (2 ell^2))
+
+Derivatives (nugget excluded): d/dsigma = 2 kappa / sigma and
+d/dell = kappa r/ell^2 (EXP), sigma^2 a^2 exp(-a)/ell (M32),
+kappa r^2/ell^3 (SE).
+
+Pins (tests/test_oracle_covariance.py): EXP and M32 against the general Matern
+form built from scipy.special.kv; SE against scipy.stats.norm.pdf; every
+derivative against a central finite difference.
+"""
+from dataclasses import dataclass
+
+import numpy as np
+
+EXP, M32, SE = 0, 1, 2
+
+
+@dataclass(frozen=True)
+class Kernel:
+    kind: int
+    sigma: float = 1.0
+    ell: float = 1.0
+    nugget: float = 0.0
+
+
+def kappa(r, kern):
+    r = np.asarray(r, dtype=np.float64)
+    s2 = kern.sigma * kern.sigma
+    if kern.kind == EXP:
+        return s2 * np.exp(-r / kern.ell)
+    if kern.kind == M32:
+        a = np.sqrt(3.0) * r / kern.ell
+        return s2 * (1.0 + a) * np.exp(-a)
+    if kern.kind == SE:
+        return s2 * np.exp(-(r * r) / (2.0 * kern.ell * kern.ell))
+    raise ValueError("unknown kernel kind %r" % (kern.kind,))
+
+
+def dkappa_dsigma(r, kern):
+    return 2.0 * kappa(r, kern) / kern.sigma
+
+
+def dkappa_dell(r, kern):
+    r = np.asarray(r, dtype=np.float64)
+    if kern.kind == EXP:
+        return kappa(r, kern) * r / (kern.ell * kern.ell)
+    if kern.kind == M32:
+        a = np.sqrt(3.0) * r / kern.ell
+        return kern.sigma * kern.sigma * a * a * np.exp(-a) / kern.ell
+    if kern.kind == SE:
+        return kappa(r, kern) * r * r / (kern.ell ** 3)
+    raise ValueError("unknown kernel kind %r" % (kern.kind,))
+
+
+def pairwise_r(xa, xb):
+    """Euclidean distances between the rows of xa (m, d) and xb (n, d)."""
+    xa = np.atleast_2d(np.asarray(xa, dtype=np.float64))
+    xb = np.atleast_2d(np.asarray(xb, dtype=np.float64))
+    diff = xa[:, None, :] - xb[None, :, :]
+    return np.sqrt(np.sum(diff * diff, axis=-1))
+
+
+def cov_matrix(xa, xb, kern, same=False, deriv=None):
+    """kappa(|xa_p - xb_q|); with same=True (xa is xb) the nugget is added on
+    the diagonal.  deriv in {None, 'sigma', 'ell'} returns the derivative of
+    the matrix with respect to that parameter instead (the nugget has none)."""
+    r = pairwise_r(xa, xb)
+    if deriv is None:
+        k = kappa(r, kern)
+        if same:
+            k = k + kern.nugget * np.eye(k.shape[0])
+        return k
+    if deriv == "sigma":
+        return dkappa_dsigma(r, kern)
+    if deriv == "ell":
+        return dkappa_dell(r, kern)
+    raise ValueError(deriv)
