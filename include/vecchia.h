@@ -1,0 +1,225 @@
+/*
+ * vecchia.h -- C ABI of the MI355X Vecchia hot path (GraphGP method).
+ *
+ * The calls follow the statement of the problem in the paper: Alg. 1 takes
+ * points X (N x d), a covariance kappa, the dense initial size n0, the
+ * neighbour matrix C ((N - n0) x k) and the parallel batches B_1..B_L, and
+ * produces v = F(xi) from white noise xi; the abstract lists the inverse
+ * application, the log-determinant and kernel-parameter derivatives as the
+ * other building blocks.
+ *
+ * Conventions shared by every call:
+ *   - Return value: VECCHIA_OK (0) or a negative status.  The message of the
+ *     last failing call on the calling thread is vecchia_last_error().  No C++
+ *     exception crosses this boundary.
+ *   - Host pointers are marked (host); device pointers (device) are HBM
+ *     allocations of the caller: the library allocates no device memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Device calls only enqueue work and return; they never synchronise the
+ *     stream, except vecchia_status().
+ *   - Storage order: every device array is indexed by storage position s in
+ *     [0, N): the dense block occupies s < n0 (in tree-slot order) and then the
+ *     batches follow in increasing depth.  graph_export() returns the mapping
+ *     storage position -> input index ("order").
+ *   - Sparse index: s' = s - n0 for s >= n0; Ns = N - n0.
+ *   - Tiled layout of the per-point k-vectors (neighbours, coefficients): for
+ *     64 consecutive sparse points, entry m of each point is contiguous:
+ *     element (s', m) lives at ((s' / 64) * kp + m) * 64 + s' % 64, where kp
+ *     is k rounded up to a compiled width (8, 16 or 32); unused entries hold
+ *     the neighbour index -1 and the coefficient 0.  Array length:
+ *     ceil(Ns / 64) * kp * 64.
+ *   - Precision: VECCHIA_FP64 computes everything in double.  VECCHIA_FP32
+ *     stores coordinates, coefficients, sigma, v and xi as float and computes
+ *     kernel values and level application in float, while the Cholesky
+ *     pivots, the conditional variances and the log-determinant stay in
+ *     double and each coefficient solve gets one refinement step with a
+ *     double-accumulated residual.  The dense block is double in both.
+ */
+#ifndef VECCHIA_H
+#define VECCHIA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------- */
+#define VECCHIA_OK            0
+#define VECCHIA_EINVAL       -1   /* bad argument, detected on the host before any launch */
+#define VECCHIA_ENOMEM       -2   /* host allocation failed or workspace too small */
+#define VECCHIA_ENOTPD       -3   /* a covariance block was not positive definite */
+#define VECCHIA_EUNSUPPORTED -4   /* valid but not compiled (e.g. k > 32, n0 > 128) */
+#define VECCHIA_EHIP         -5   /* a HIP runtime call failed */
+#define VECCHIA_EBUDGET      -6   /* serving admission: request exceeds the HBM budget */
+
+#define VECCHIA_FP64 0
+#define VECCHIA_FP32 1
+
+#define VECCHIA_KMAX  32          /* largest compiled neighbour count */
+#define VECCHIA_N0MAX 128         /* largest dense block (FP64 n0 x n0 in one workgroup's LDS) */
+
+/* ---- covariance ---------------------------------------------------------- */
+/* Stationary kernel kappa(r) of Sec. 2.1 (forms named by the workloads):
+ *   kind 0 EXP: sigma^2 exp(-r/ell)
+ *   kind 1 M32: sigma^2 (1 + sqrt3 r/ell) exp(-sqrt3 r/ell)
+ *   kind 2 SE : sigma^2 exp(-r^2/(2 ell^2))
+ * `nugget` is added only on the diagonal (a point with itself). */
+typedef struct vecchia_kernel {
+    int32_t kind;
+    double sigma;
+    double ell;
+    double nugget;
+} vecchia_kernel;
+
+/* ---- graph (host, int32) -------------------------------------------------- */
+typedef struct vecchia_graph vecchia_graph;   /* opaque, owned by the library */
+
+/* Sec. 2.2 and Sec. 2.1: orders the N points of x (host, row-major N x d,
+ * finite doubles) in the bit-reversed left-balanced k-d tree order (split on
+ * the dimension of widest extent, median by (coordinate, input index)),
+ * finds for every slot i >= n0 the k nearest preceding slots (squared
+ * distance ((dx*dx + dy*dy) + dz*dz) in double, ties to the smaller slot;
+ * fewer than k predecessors pad with -1), computes the depths
+ * d_i = 1 + max_{j in c(i)} d_j (Sec. 2.2, "Batch construction") and the
+ * storage order (dense block, then batches by depth; inside a batch, in-order
+ * rank of the tree, which is spatially coherent).
+ * 1 <= d <= 3, 1 <= k <= VECCHIA_KMAX, 1 <= n0 <= n < 2^31.  n_threads <= 0
+ * uses every hardware thread.  On success *out owns the graph; free it with
+ * graph_free().  Errors: EINVAL (arguments, non-finite coordinates), ENOMEM. */
+int graph_build(const double* x, int64_t n, int32_t d, int32_t k, int32_t n0,
+                int32_t n_threads, vecchia_graph** out);
+
+/* Sizes of a built graph (any pointer may be NULL).  kp = padded width of the
+ * tiled layout; n_levels = number of sparse batches L. */
+int graph_info(const vecchia_graph* g, int64_t* n, int32_t* d, int32_t* k, int32_t* kp,
+               int32_t* n0, int32_t* n_levels);
+
+/* Storage maps (host arrays, caller-allocated, any may be NULL):
+ *   order[N]          storage position -> input index
+ *   slot[N]           storage position -> tree slot (generation order)
+ *   level_ptr[L + 2]  batch boundaries: level_ptr[0] = 0, level_ptr[1] = n0,
+ *                     batch l (1..L) is [level_ptr[l], level_ptr[l+1])
+ *   depth[N]          depth of each storage position (0 for the dense block) */
+int graph_export(const vecchia_graph* g, int32_t* order, int32_t* slot, int32_t* level_ptr,
+                 int32_t* depth);
+
+/* Neighbour indices in storage positions (host, caller-allocated):
+ * layout 0 = row-major Ns x k, rows in sparse-index order, each row in
+ * ascending (distance, slot); layout 1 = the tiled device layout (length
+ * ceil(Ns/64) * kp * 64). */
+int graph_export_nbr(const vecchia_graph* g, int32_t layout, int32_t* nbr);
+
+/* Coordinates in storage order, 3 per point (zero padded for d < 3), as
+ * double (precision VECCHIA_FP64) or float (VECCHIA_FP32): host, N x 3. */
+int graph_export_points(const vecchia_graph* g, int32_t precision, void* xs);
+
+/* Children lists for the reverse sweep of the adjoint (host): for storage
+ * position j, child[child_ptr[j] .. child_ptr[j+1]) are the packed entries
+ * s' * kp + m of every sparse point s' whose m-th neighbour is j, ascending.
+ * child_ptr has N + 1 entries; child has Ns * k entries at most (the exact
+ * count is child_ptr[N]).  EUNSUPPORTED if Ns * kp >= 2^31. */
+int graph_export_children(const vecchia_graph* g, int64_t* child_ptr, int32_t* child);
+
+/* Host time spent in the phases of graph_build, seconds: tree, neighbours,
+ * depth, storage order.  times has 4 entries. */
+int graph_build_times(const vecchia_graph* g, double* times);
+
+void graph_free(vecchia_graph* g);
+
+/* ---- device factor ---------------------------------------------------------- */
+/* A view of one factored point set.  Every pointer except level_ptr is a
+ * device pointer owned by the caller; the view itself is plain data. */
+typedef struct vecchia_view {
+    int64_t n;                 /* N */
+    int32_t k;                 /* neighbours per point */
+    int32_t kp;                /* padded width of the tiled layout (graph_info) */
+    int32_t n0;                /* dense block size */
+    int32_t n_levels;          /* L */
+    int32_t precision;         /* VECCHIA_FP64 or VECCHIA_FP32 */
+    int32_t reserved;
+    const void* x;             /* (device) N x 3 coordinates in storage order, double or float */
+    const int32_t* nbr;        /* (device) tiled neighbour indices (graph_export_nbr layout 1) */
+    const int32_t* level_ptr;  /* (host)   L + 2 batch boundaries (graph_export) */
+    const int64_t* child_ptr;  /* (device) N + 1, only needed by vecchia_backward, else NULL */
+    const int32_t* child;      /* (device) packed children, only for vecchia_backward, else NULL */
+    void* workspace;           /* (device) vecchia_workspace_bytes() bytes, 256-byte aligned */
+    size_t workspace_bytes;
+    vecchia_kernel kernel;     /* written by vecchia_factor */
+} vecchia_view;
+
+/* Bytes of device workspace that hold a factor: coefficients b (tiled),
+ * sigma, the dense factor L0 (n0 x n0 double), log-determinant partials and a
+ * status word. */
+int vecchia_workspace_bytes(int64_t n, int32_t k, int32_t n0, int32_t precision, size_t* bytes);
+
+/* Eq. (2) for every sparse point at once, plus the dense initial batch:
+ * gathers the coordinates of each point and of its k neighbours, assembles
+ * K_cc, k_ci and K_ii, factors K_cc = L L^T, solves y = L^-1 k_ci,
+ * b = L^-T y, sigma^2 = K_ii - y.y, and L0 = chol(K[0:n0, 0:n0]).  Writes the
+ * workspace and view->kernel.  A non-positive pivot or conditional variance
+ * is recorded in the workspace status word (see vecchia_status); nothing is
+ * jittered.  Errors: EINVAL (view/kernel), ENOMEM (workspace too small),
+ * EUNSUPPORTED, EHIP (launch failure). */
+int vecchia_factor(vecchia_view* view, const vecchia_kernel* kern, void* stream);
+
+/* Alg. 1: v[0:n0] = L0 xi[0:n0], then for every batch l = 1..L in order,
+ * v_i = b_i . v[c(i)] + sigma_i xi_i.  xi and v are device arrays of N
+ * elements (double or float per view->precision) in storage order; they must
+ * not overlap. */
+int vecchia_forward(const vecchia_view* view, const void* xi, void* v, void* stream);
+
+/* Inverse application xi = F^-1(v): xi[0:n0] = L0^-1 v[0:n0] and
+ * xi_i = (v_i - b_i . v[c(i)]) / sigma_i for every sparse point at once. */
+int vecchia_inverse(const vecchia_view* view, const void* v, void* xi, void* stream);
+
+/* log det of the Vecchia covariance F F^T = 2 (sum log L0_jj + sum log sigma_i),
+ * summed in double with compensation, written to out (device, 1 double). */
+int vecchia_logdet(const vecchia_view* view, double* out, void* stream);
+
+/* Reverse-mode derivatives (Sec. 2.3) of
+ *     <v_bar, F xi> + <xi_bar_in, F^-1 v> + logdet_bar * logdet
+ * with respect to xi, v and theta = (sigma, ell):
+ *   xi_bar  (device, N)   = F^T v_bar              (NULL allowed if v_bar NULL)
+ *   v_bar_out (device, N) = F^-T xi_bar_in         (NULL allowed if xi_bar_in NULL)
+ *   theta_bar (device, 2 doubles) = d/d(sigma, ell), accumulated in double.
+ * xi and v are the forward pair (v = F xi) or the inverse pair; v_bar and
+ * xi_bar_in may be NULL.  Needs view->child_ptr and view->child.  scratch is a
+ * device buffer of vecchia_backward_scratch_bytes() bytes. */
+int vecchia_backward_scratch_bytes(const vecchia_view* view, size_t* bytes);
+int vecchia_backward(const vecchia_view* view, const vecchia_kernel* kern,
+                     const void* xi, const void* v, const void* v_bar, const void* xi_bar_in,
+                     double logdet_bar, void* xi_bar, void* v_bar_out, double* theta_bar,
+                     void* scratch, size_t scratch_bytes, void* stream);
+
+/* Synchronises `stream`, then reads the workspace status word.  Returns
+ * VECCHIA_OK, or VECCHIA_ENOTPD with *first_bad_slot = the smallest storage
+ * position whose pivot or conditional variance was not positive (-1 if
+ * none; the dense block reports its first bad pivot row). */
+int vecchia_status(const vecchia_view* view, void* stream, int64_t* first_bad_slot);
+
+/* Padded width used for a neighbour count k (8, 16 or 32), or -1. */
+int32_t vecchia_padded_k(int32_t k);
+
+/* Per-kernel timing: when enabled, every launch made by the library is
+ * bracketed by HIP events on its stream and its duration is accumulated per
+ * kernel name (milliseconds).  Reading the totals synchronises the device.
+ * names: buffer of `cap` bytes receiving '\n'-separated names. */
+int vecchia_profile_enable(int32_t on);
+int vecchia_profile_read(char* names, size_t cap, double* total_ms, int64_t* launches, int32_t max_kernels,
+                         int32_t* n_kernels);
+int vecchia_profile_reset(void);
+
+/* sizeof(vecchia_view) and sizeof(vecchia_kernel) as compiled, for bindings
+ * that mirror the structs (ABI check). */
+int vecchia_abi_sizes(size_t* view_bytes, size_t* kernel_bytes);
+
+const char* vecchia_last_error(void);
+const char* vecchia_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VECCHIA_H */

@@ -1,0 +1,312 @@
+// extern "C" entry points of the device side: argument validation on the
+// host, workspace carving, launch sequencing and optional per-kernel timing.
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "status.h"
+
+using namespace vk;
+
+namespace {
+
+// ---- per-kernel timing with HIP events on the launch stream ---------------
+struct Pending {
+    const char* name;
+    hipEvent_t a, b;
+};
+struct KernelTotal {
+    std::string name;
+    double ms = 0.0;
+    int64_t launches = 0;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<Pending> g_pending;
+std::vector<hipEvent_t> g_event_pool;
+std::vector<KernelTotal> g_totals;
+
+hipEvent_t take_event() {
+    if (!g_event_pool.empty()) {
+        hipEvent_t e = g_event_pool.back();
+        g_event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+template <class F>
+hipError_t timed(const char* name, hipStream_t s, F&& launch) {
+    bool on;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        on = g_prof_on;
+    }
+    if (!on) return launch();
+    hipEvent_t a, b;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        a = take_event();
+        b = take_event();
+    }
+    if (!a || !b) return launch();
+    hipEventRecord(a, s);
+    hipError_t err = launch();
+    hipEventRecord(b, s);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_pending.push_back(Pending{name, a, b});
+    return err;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+    return vecchia_set_error(VECCHIA_EHIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+int check_kernel(const vecchia_kernel* k) {
+    if (!k) return vecchia_set_error(VECCHIA_EINVAL, "kernel is NULL");
+    if (k->kind < 0 || k->kind > 2) return vecchia_set_error(VECCHIA_EINVAL, "kernel kind %d not in {0,1,2}", k->kind);
+    if (!(k->sigma > 0.0) || !std::isfinite(k->sigma)) return vecchia_set_error(VECCHIA_EINVAL, "kernel sigma must be > 0");
+    if (!(k->ell > 0.0) || !std::isfinite(k->ell)) return vecchia_set_error(VECCHIA_EINVAL, "kernel ell must be > 0");
+    if (!(k->nugget >= 0.0) || !std::isfinite(k->nugget)) return vecchia_set_error(VECCHIA_EINVAL, "kernel nugget must be >= 0");
+    return VECCHIA_OK;
+}
+
+int check_view(const vecchia_view* v, Layout* lay, const char* who) {
+    if (!v) return vecchia_set_error(VECCHIA_EINVAL, "%s: view is NULL", who);
+    if (v->n < 1 || v->n >= (int64_t(1) << 31)) return vecchia_set_error(VECCHIA_EINVAL, "%s: need 1 <= N < 2^31", who);
+    if (v->k < 1 || v->k > VECCHIA_KMAX) return vecchia_set_error(VECCHIA_EINVAL, "%s: need 1 <= k <= %d", who, VECCHIA_KMAX);
+    if (v->kp != vecchia_padded_k(v->k))
+        return vecchia_set_error(VECCHIA_EINVAL, "%s: kp=%d does not match k=%d (expected %d)", who, v->kp, v->k,
+                                 vecchia_padded_k(v->k));
+    if (v->n0 < 1 || v->n0 > v->n) return vecchia_set_error(VECCHIA_EINVAL, "%s: need 1 <= n0 <= N", who);
+    if (v->n0 > VECCHIA_N0MAX)
+        return vecchia_set_error(VECCHIA_EUNSUPPORTED, "%s: n0=%d exceeds the compiled maximum %d", who, v->n0, VECCHIA_N0MAX);
+    if (v->precision != VECCHIA_FP64 && v->precision != VECCHIA_FP32)
+        return vecchia_set_error(VECCHIA_EINVAL, "%s: precision must be VECCHIA_FP64 or VECCHIA_FP32", who);
+    if (!v->x || !v->nbr || !v->level_ptr || !v->workspace)
+        return vecchia_set_error(VECCHIA_EINVAL, "%s: x, nbr, level_ptr and workspace must be set", who);
+    if (v->n_levels < 0) return vecchia_set_error(VECCHIA_EINVAL, "%s: n_levels < 0", who);
+    const int32_t* lp = v->level_ptr;
+    if (lp[0] != 0 || lp[1] != v->n0 || lp[v->n_levels + 1] != v->n)
+        return vecchia_set_error(VECCHIA_EINVAL, "%s: level_ptr must start 0, n0 and end at N", who);
+    for (int l = 1; l <= v->n_levels; ++l)
+        if (lp[l + 1] < lp[l]) return vecchia_set_error(VECCHIA_EINVAL, "%s: level_ptr not ascending at %d", who, l);
+    *lay = workspace_layout(v->n, v->kp, v->n0, v->precision);
+    if (v->workspace_bytes < lay->total)
+        return vecchia_set_error(VECCHIA_ENOMEM, "%s: workspace has %zu bytes, needs %zu", who, v->workspace_bytes, lay->total);
+    if (reinterpret_cast<uintptr_t>(v->workspace) & 255)
+        return vecchia_set_error(VECCHIA_EINVAL, "%s: workspace must be 256-byte aligned", who);
+    return VECCHIA_OK;
+}
+
+template <typename T>
+T* ws(const vecchia_view* v, size_t off) {
+    return reinterpret_cast<T*>(static_cast<char*>(v->workspace) + off);
+}
+
+}  // namespace
+
+extern "C" int vecchia_workspace_bytes(int64_t n, int32_t k, int32_t n0, int32_t precision, size_t* bytes) {
+    if (!bytes) return vecchia_set_error(VECCHIA_EINVAL, "vecchia_workspace_bytes: bytes is NULL");
+    const int kp = vecchia_padded_k(k);
+    if (kp < 0) return vecchia_set_error(VECCHIA_EINVAL, "vecchia_workspace_bytes: k=%d out of range", k);
+    if (n < 1 || n0 < 1 || n0 > n) return vecchia_set_error(VECCHIA_EINVAL, "vecchia_workspace_bytes: need 1 <= n0 <= N");
+    if (precision != VECCHIA_FP64 && precision != VECCHIA_FP32)
+        return vecchia_set_error(VECCHIA_EINVAL, "vecchia_workspace_bytes: bad precision");
+    *bytes = workspace_layout(n, kp, n0, precision).total;
+    return VECCHIA_OK;
+}
+
+extern "C" int vecchia_factor(vecchia_view* view, const vecchia_kernel* kern, void* stream) {
+    vecchia_clear_error();
+    Layout lay;
+    int rc = check_view(view, &lay, "vecchia_factor");
+    if (rc) return rc;
+    if ((rc = check_kernel(kern))) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    view->kernel = *kern;
+    hipError_t e = timed("factor_dense", s, [&] {
+        return launch_factor_dense(view->precision, kern->kind, view->x, view->n0, *kern, ws<double>(view, lay.l0),
+                                   ws<double>(view, lay.ld0), ws<uint64_t>(view, lay.status), s);
+    });
+    if (e != hipSuccess) return hip_fail(e, "vecchia_factor (dense block)");
+    FactorLaunch a;
+    a.precision = view->precision;
+    a.kp = view->kp;
+    a.kind = kern->kind;
+    a.n = view->n;
+    a.ns = lay.ns;
+    a.n0 = view->n0;
+    a.x = view->x;
+    a.nbr = view->nbr;
+    a.b = ws<char>(view, lay.b);
+    a.sigma = ws<char>(view, lay.sigma);
+    a.ldpart = ws<double>(view, lay.ldpart);
+    a.status = ws<uint64_t>(view, lay.status);
+    a.kern = *kern;
+    if (lay.ns > 0) {
+        e = timed("factor_sparse", s, [&] { return launch_factor_sparse(a, s); });
+        if (e != hipSuccess) return hip_fail(e, "vecchia_factor (sparse points)");
+    }
+    return VECCHIA_OK;
+}
+
+extern "C" int vecchia_forward(const vecchia_view* view, const void* xi, void* v, void* stream) {
+    vecchia_clear_error();
+    Layout lay;
+    int rc = check_view(view, &lay, "vecchia_forward");
+    if (rc) return rc;
+    if (!xi || !v) return vecchia_set_error(VECCHIA_EINVAL, "vecchia_forward: xi and v must be set");
+    if (xi == v) return vecchia_set_error(VECCHIA_EINVAL, "vecchia_forward: xi and v must not alias");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = timed("forward_dense", s, [&] {
+        return launch_forward_dense(view->precision, ws<double>(view, lay.l0), view->n0, xi, v, s);
+    });
+    if (e != hipSuccess) return hip_fail(e, "vecchia_forward (dense block)");
+    const int32_t* lp = view->level_ptr;
+    for (int l = 1; l <= view->n_levels; ++l) {
+        const int64_t a = lp[l] - view->n0, b = lp[l + 1] - view->n0;
+        e = timed("forward_level", s, [&] {
+            return launch_forward_level(view->precision, view->kp, view->nbr, ws<char>(view, lay.b),
+                                        ws<char>(view, lay.sigma), xi, v, view->n0, a, b, s);
+        });
+        if (e != hipSuccess) return hip_fail(e, "vecchia_forward (level)");
+    }
+    return VECCHIA_OK;
+}
+
+extern "C" int vecchia_inverse(const vecchia_view* view, const void* v, void* xi, void* stream) {
+    vecchia_clear_error();
+    Layout lay;
+    int rc = check_view(view, &lay, "vecchia_inverse");
+    if (rc) return rc;
+    if (!xi || !v) return vecchia_set_error(VECCHIA_EINVAL, "vecchia_inverse: xi and v must be set");
+    if (xi == v) return vecchia_set_error(VECCHIA_EINVAL, "vecchia_inverse: xi and v must not alias");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = timed("inverse_dense", s, [&] {
+        return launch_inverse_dense(view->precision, ws<double>(view, lay.l0), view->n0, v, xi, s);
+    });
+    if (e != hipSuccess) return hip_fail(e, "vecchia_inverse (dense block)");
+    e = timed("inverse_sparse", s, [&] {
+        return launch_inverse_sparse(view->precision, view->kp, view->nbr, ws<char>(view, lay.b),
+                                     ws<char>(view, lay.sigma), v, xi, view->n0, lay.ns, s);
+    });
+    if (e != hipSuccess) return hip_fail(e, "vecchia_inverse (sparse points)");
+    return VECCHIA_OK;
+}
+
+extern "C" int vecchia_logdet(const vecchia_view* view, double* out, void* stream) {
+    vecchia_clear_error();
+    Layout lay;
+    int rc = check_view(view, &lay, "vecchia_logdet");
+    if (rc) return rc;
+    if (!out) return vecchia_set_error(VECCHIA_EINVAL, "vecchia_logdet: out is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = timed("logdet", s, [&] {
+        return launch_logdet(ws<double>(view, lay.ldpart), lay.ns > 0 ? lay.nparts : 0, ws<double>(view, lay.ld0), out, s);
+    });
+    if (e != hipSuccess) return hip_fail(e, "vecchia_logdet");
+    return VECCHIA_OK;
+}
+
+extern "C" int vecchia_status(const vecchia_view* view, void* stream, int64_t* first_bad_slot) {
+    vecchia_clear_error();
+    Layout lay;
+    int rc = check_view(view, &lay, "vecchia_status");
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    uint64_t st[2] = {0, 0};
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "vecchia_status (stream)");
+    e = hipMemcpy(st, ws<uint64_t>(view, lay.status), sizeof(st), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "vecchia_status (copy)");
+    if (first_bad_slot) *first_bad_slot = st[0] == kStatusNone ? -1 : (int64_t)st[0];
+    if (st[0] != kStatusNone)
+        return vecchia_set_error(VECCHIA_ENOTPD, "covariance not positive definite at storage position %llu (%llu points)",
+                                 (unsigned long long)st[0], (unsigned long long)st[1]);
+    return VECCHIA_OK;
+}
+
+extern "C" int vecchia_profile_enable(int32_t on) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = on != 0;
+    return VECCHIA_OK;
+}
+
+static int drain_pending() {
+    std::vector<Pending> todo;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        todo.swap(g_pending);
+    }
+    for (const Pending& p : todo) {
+        hipError_t e = hipEventSynchronize(p.b);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, p.a, p.b);
+        if (e != hipSuccess) return hip_fail(e, "vecchia_profile_read");
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        KernelTotal* t = nullptr;
+        for (auto& k : g_totals)
+            if (k.name == p.name) t = &k;
+        if (!t) {
+            g_totals.push_back(KernelTotal{p.name, 0.0, 0});
+            t = &g_totals.back();
+        }
+        t->ms += ms;
+        t->launches += 1;
+        g_event_pool.push_back(p.a);
+        g_event_pool.push_back(p.b);
+    }
+    return VECCHIA_OK;
+}
+
+extern "C" int vecchia_profile_read(char* names, size_t cap, double* total_ms, int64_t* launches, int32_t max_kernels,
+                                    int32_t* n_kernels) {
+    int rc = drain_pending();
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    std::string joined;
+    int n = 0;
+    for (const auto& t : g_totals) {
+        if (n >= max_kernels) break;
+        if (total_ms) total_ms[n] = t.ms;
+        if (launches) launches[n] = t.launches;
+        joined += t.name;
+        joined += '\n';
+        ++n;
+    }
+    if (n_kernels) *n_kernels = n;
+    if (names && cap > 0) {
+        const size_t m = std::min(cap - 1, joined.size());
+        std::memcpy(names, joined.data(), m);
+        names[m] = 0;
+    }
+    return VECCHIA_OK;
+}
+
+extern "C" int vecchia_profile_reset(void) {
+    int rc = drain_pending();
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_totals.clear();
+    return rc;
+}
+
+extern "C" int vecchia_backward_scratch_bytes(const vecchia_view* view, size_t* bytes) {
+    (void)view;
+    (void)bytes;
+    return vecchia_set_error(VECCHIA_EUNSUPPORTED, "vecchia_backward_scratch_bytes: adjoint not built yet");
+}
+
+extern "C" int vecchia_backward(const vecchia_view* view, const vecchia_kernel* kern, const void* xi, const void* v,
+                                const void* v_bar, const void* xi_bar_in, double logdet_bar, void* xi_bar,
+                                void* v_bar_out, double* theta_bar, void* scratch, size_t scratch_bytes,
+                                void* stream) {
+    (void)view, (void)kern, (void)xi, (void)v, (void)v_bar, (void)xi_bar_in, (void)logdet_bar, (void)xi_bar;
+    (void)v_bar_out, (void)theta_bar, (void)scratch, (void)scratch_bytes, (void)stream;
+    return vecchia_set_error(VECCHIA_EUNSUPPORTED, "vecchia_backward: adjoint not built yet");
+}

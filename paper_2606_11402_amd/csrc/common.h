@@ -1,0 +1,135 @@
+// Shared definitions of the HIP side: covariance evaluation, workspace layout
+// and launch plumbing.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "vecchia.h"
+
+namespace vk {
+
+constexpr int kBlock = 256;           // threads per workgroup of the point kernels
+constexpr int kTile = 64;             // points per tile of the tiled layout
+constexpr uint64_t kStatusNone = ~0ull;
+
+// Lanes per point of the factor kernels, by precision and padded width.
+// Lane r of a group owns rows r, r+P, ...; chosen so that the packed lower
+// triangle of K_cc (P*R*(R+1)/2 values per lane, R = kp/P) stays in registers.
+__host__ __device__ constexpr int factor_lanes(int precision, int kp) {
+    return precision == VECCHIA_FP32 ? (kp <= 8 ? 1 : 4) : (kp <= 8 ? 1 : (kp <= 16 ? 4 : 8));
+}
+
+// Device workspace holding one factor.  Offsets are 256-byte aligned.
+struct Layout {
+    int64_t ns = 0, ntiles = 0, nparts = 0;
+    size_t esz = 0;
+    size_t b = 0, sigma = 0, l0 = 0, ldpart = 0, ld0 = 0, status = 0, total = 0;
+};
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+inline Layout workspace_layout(int64_t n, int kp, int n0, int precision) {
+    Layout w;
+    w.ns = n - n0;
+    w.ntiles = (w.ns + kTile - 1) / kTile;
+    w.esz = precision == VECCHIA_FP64 ? 8 : 4;
+    const int pts_per_block = kBlock / factor_lanes(precision, kp);
+    w.nparts = (w.ns + pts_per_block - 1) / pts_per_block;
+    size_t off = 0;
+    w.b = off;
+    off = align256(off + (size_t)w.ntiles * kp * kTile * w.esz);
+    w.sigma = off;
+    off = align256(off + (size_t)w.ntiles * kTile * w.esz);
+    w.l0 = off;
+    off = align256(off + (size_t)n0 * n0 * sizeof(double));
+    w.ldpart = off;
+    off = align256(off + (size_t)(w.nparts > 0 ? w.nparts : 1) * sizeof(double));
+    w.ld0 = off;
+    off = align256(off + sizeof(double));
+    w.status = off;
+    off = align256(off + 2 * sizeof(uint64_t));
+    w.total = off;
+    return w;
+}
+
+// Covariance parameters, pre-scaled on the host.
+template <typename T>
+struct Cov {
+    T s2;          // sigma^2
+    T inv_ell;     // 1/ell
+    T c_m32;       // sqrt(3)/ell
+    T c_se;        // -1/(2 ell^2)
+};
+
+template <typename T>
+inline Cov<T> make_cov(const vecchia_kernel& k) {
+    Cov<T> c;
+    c.s2 = (T)(k.sigma * k.sigma);
+    c.inv_ell = (T)(1.0 / k.ell);
+    c.c_m32 = (T)(1.7320508075688772 / k.ell);
+    c.c_se = (T)(-0.5 / (k.ell * k.ell));
+    return c;
+}
+
+// 1/sqrt(d) in double: hardware estimate plus one Newton-Raphson step,
+// y1 = y0 + y0 (1 - d y0^2) / 2, which squares the relative error of y0.
+__device__ __forceinline__ double rsqrt_f64(double d) {
+    const double y0 = __builtin_amdgcn_rsq(d);
+    const double e = fma(-d, y0 * y0, 1.0);
+    return fma(0.5 * y0, e, y0);
+}
+
+__device__ __forceinline__ float dev_exp(float x) { return expf(x); }
+__device__ __forceinline__ double dev_exp(double x) { return exp(x); }
+__device__ __forceinline__ float dev_sqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ double dev_sqrt(double x) { return sqrt(x); }
+
+// kappa(r) from the squared distance r2 (no nugget).
+template <int KIND, typename T>
+__device__ __forceinline__ T cov_r2(T r2, const Cov<T>& c) {
+    if constexpr (KIND == 0) {
+        return c.s2 * dev_exp(-dev_sqrt(r2) * c.inv_ell);
+    } else if constexpr (KIND == 1) {
+        const T a = dev_sqrt(r2) * c.c_m32;
+        return c.s2 * (T(1) + a) * dev_exp(-a);
+    } else {
+        return c.s2 * dev_exp(r2 * c.c_se);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T sqdist3(T a0, T a1, T a2, T b0, T b1, T b2) {
+    const T d0 = a0 - b0, d1 = a1 - b1, d2 = a2 - b2;
+    return d0 * d0 + d1 * d1 + d2 * d2;
+}
+
+}  // namespace vk
+
+// Launchers implemented in the .hip files (all enqueue on `stream`).
+namespace vk {
+struct FactorLaunch {
+    int precision, kp, kind;
+    int64_t n, ns;
+    int n0;
+    const void* x;
+    const int32_t* nbr;
+    void* b;
+    void* sigma;
+    double* ldpart;
+    uint64_t* status;
+    vecchia_kernel kern;
+};
+hipError_t launch_factor_sparse(const FactorLaunch& a, hipStream_t stream);
+hipError_t launch_factor_dense(int precision, int kind, const void* x, int n0, const vecchia_kernel& kern,
+                               double* l0, double* ld0, uint64_t* status, hipStream_t stream);
+hipError_t launch_forward_dense(int precision, const double* l0, int n0, const void* xi, void* v, hipStream_t stream);
+hipError_t launch_forward_level(int precision, int kp, const int32_t* nbr, const void* b, const void* sigma,
+                                const void* xi, void* v, int n0, int64_t s_begin, int64_t s_end, hipStream_t stream);
+hipError_t launch_inverse_dense(int precision, const double* l0, int n0, const void* v, void* xi, hipStream_t stream);
+hipError_t launch_inverse_sparse(int precision, int kp, const int32_t* nbr, const void* b, const void* sigma,
+                                 const void* v, void* xi, int n0, int64_t ns, hipStream_t stream);
+hipError_t launch_logdet(const double* ldpart, int64_t nparts, const double* ld0, double* out, hipStream_t stream);
+}  // namespace vk

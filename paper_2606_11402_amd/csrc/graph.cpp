@@ -1,0 +1,475 @@
+// Host graph build of the Vecchia hot path: bit-reversed k-d tree order,
+// k nearest preceding neighbours, depth batches and storage order.
+//
+// Sec. 2.2 ("Tree ordering", "Bit-reversed ordering"): the slot t at tree
+// level l = floor(log2(t+1)) has children t + 2^l (left) and t + 2^(l+1)
+// (right); with this layout every level but the last is full, the last one is
+// filled in bit-reversed position order, and each node's left subtree holds
+// floor(n/2) of the n points under it.  A node therefore keeps the point of
+// rank floor(n/2) along its split dimension; the split dimension is the one
+// of widest extent (lowest index on ties) and ranks are taken on the key
+// (coordinate, input index).
+//
+// Sec. 2.1: c(i) = the k nearest points among the slots j < i, key (D, j)
+// with D = ((dx*dx + dy*dy) + dz*dz) in double and no contraction (this file
+// is compiled with -ffp-contract=off).  Because every parent precedes its
+// children, the slots {0..i-1} form a k-d tree themselves and the query walks
+// only that prefix.  A far subtree is skipped only when the squared distance
+// to its splitting plane is strictly greater than the current k-th best D:
+// that plane distance, rounded, is a lower bound of the rounded D of every
+// point behind the plane, so ties are never lost and the result equals the
+// brute-force search bit for bit.
+//
+// Sec. 2.2 ("Batch construction"): d_i = 1 + max_{j in c(i)} d_j in slot
+// order; the dense block (slots < n0) has depth 0.  Storage order: the dense
+// block in slot order, then the batches in increasing depth; inside a batch
+// the points follow the in-order sequence of the tree, which keeps spatial
+// neighbours close in memory for the gathers on the device.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "status.h"
+#include "vecchia.h"
+
+struct vecchia_graph {
+    int64_t n = 0;
+    int32_t d = 0, k = 0, kp = 0, n0 = 0, n_levels = 0;
+    std::vector<double> xs;            // slot order, 3 per slot (zero padded)
+    std::vector<int32_t> tree_perm;    // slot -> input index
+    std::vector<int8_t> sdim;          // slot -> split dimension
+    std::vector<int32_t> nbr;          // (n - n0) x k neighbour slots, row r = slot n0 + r
+    std::vector<int32_t> depth;        // slot -> depth
+    std::vector<int32_t> order;        // storage -> slot
+    std::vector<int32_t> pos;          // slot -> storage
+    std::vector<int32_t> level_ptr;    // n_levels + 2
+    double times[4] = {0, 0, 0, 0};
+};
+
+namespace {
+
+inline int tree_level(int64_t t) { return 63 - __builtin_clzll((uint64_t)(t + 1)); }
+inline int64_t left_child(int64_t t) { return t + (int64_t(1) << tree_level(t)); }
+inline int64_t right_child(int64_t t) { return t + (int64_t(2) << tree_level(t)); }
+
+template <class F>
+void parallel_for(int64_t n, int64_t grain, int nthreads, F&& f) {
+    if (n <= 0) return;
+    if (nthreads <= 1 || n <= grain) {
+        f(int64_t(0), n);
+        return;
+    }
+    std::atomic<int64_t> next(0);
+    auto work = [&]() {
+        for (;;) {
+            int64_t a = next.fetch_add(grain);
+            if (a >= n) break;
+            f(a, std::min(n, a + grain));
+        }
+    };
+    int nt = (int)std::min<int64_t>(nthreads, (n + grain - 1) / grain);
+    std::vector<std::thread> th;
+    th.reserve(nt - 1);
+    for (int t = 1; t < nt; ++t) th.emplace_back(work);
+    work();
+    for (auto& t : th) t.join();
+}
+
+struct TreePoint {
+    double c[3];
+    int32_t id;
+    int32_t pad;
+};
+
+struct Task {
+    int64_t slot, lo, hi;
+};
+
+double seconds_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// Split dimension of pts[lo, hi): widest extent, lowest index on ties.
+int widest_dim(const TreePoint* pts, int64_t lo, int64_t hi, int d, int nthreads) {
+    double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    const int64_t big = int64_t(1) << 22;
+    if (hi - lo >= big && nthreads > 1) {
+        int64_t chunks = (hi - lo + big - 1) / big;
+        std::vector<double> pmn(chunks * 3, INFINITY), pmx(chunks * 3, -INFINITY);
+        parallel_for(chunks, 1, nthreads, [&](int64_t a, int64_t b) {
+            for (int64_t ch = a; ch < b; ++ch) {
+                int64_t s = lo + ch * big, e = std::min(hi, s + big);
+                for (int64_t p = s; p < e; ++p)
+                    for (int c = 0; c < d; ++c) {
+                        pmn[ch * 3 + c] = std::min(pmn[ch * 3 + c], pts[p].c[c]);
+                        pmx[ch * 3 + c] = std::max(pmx[ch * 3 + c], pts[p].c[c]);
+                    }
+            }
+        });
+        for (int64_t ch = 0; ch < chunks; ++ch)
+            for (int c = 0; c < d; ++c) {
+                mn[c] = std::min(mn[c], pmn[ch * 3 + c]);
+                mx[c] = std::max(mx[c], pmx[ch * 3 + c]);
+            }
+    } else {
+        for (int64_t p = lo; p < hi; ++p)
+            for (int c = 0; c < d; ++c) {
+                mn[c] = std::min(mn[c], pts[p].c[c]);
+                mx[c] = std::max(mx[c], pts[p].c[c]);
+            }
+    }
+    int best = 0;
+    double bext = mx[0] - mn[0];
+    for (int c = 1; c < d; ++c) {
+        double e = mx[c] - mn[c];
+        if (e > bext) {
+            bext = e;
+            best = c;
+        }
+    }
+    return best;
+}
+
+void build_tree(vecchia_graph& g, const double* x, int nthreads) {
+    const int64_t n = g.n;
+    const int d = g.d;
+    std::vector<TreePoint> pts(n);
+    parallel_for(n, 1 << 16, nthreads, [&](int64_t a, int64_t b) {
+        for (int64_t i = a; i < b; ++i) {
+            for (int c = 0; c < 3; ++c) pts[i].c[c] = c < d ? x[i * d + c] : 0.0;
+            pts[i].id = (int32_t)i;
+            pts[i].pad = 0;
+        }
+    });
+    g.tree_perm.assign(n, -1);
+    g.sdim.assign(n, 0);
+    std::vector<Task> cur{{0, 0, n}}, nxt;
+    while (!cur.empty()) {
+        nxt.assign(cur.size() * 2, Task{-1, 0, 0});
+        // few large tasks: give each the whole pool for its extent scan
+        int inner = cur.size() < (size_t)nthreads ? std::max(1, nthreads / (int)cur.size()) : 1;
+        parallel_for((int64_t)cur.size(), 1, nthreads, [&](int64_t a, int64_t b) {
+            for (int64_t ti = a; ti < b; ++ti) {
+                const Task tk = cur[ti];
+                const int64_t cnt = tk.hi - tk.lo;
+                const int s = widest_dim(pts.data(), tk.lo, tk.hi, d, inner);
+                const int64_t m = cnt / 2;
+                std::nth_element(pts.begin() + tk.lo, pts.begin() + tk.lo + m, pts.begin() + tk.hi,
+                                 [s](const TreePoint& p, const TreePoint& q) {
+                                     return p.c[s] < q.c[s] || (p.c[s] == q.c[s] && p.id < q.id);
+                                 });
+                g.tree_perm[tk.slot] = pts[tk.lo + m].id;
+                g.sdim[tk.slot] = (int8_t)s;
+                if (m > 0) nxt[2 * ti] = Task{left_child(tk.slot), tk.lo, tk.lo + m};
+                if (cnt - m - 1 > 0) nxt[2 * ti + 1] = Task{right_child(tk.slot), tk.lo + m + 1, tk.hi};
+            }
+        });
+        cur.clear();
+        for (const Task& t : nxt)
+            if (t.slot >= 0) cur.push_back(t);
+    }
+    g.xs.resize(n * 3);
+    parallel_for(n, 1 << 16, nthreads, [&](int64_t a, int64_t b) {
+        for (int64_t t = a; t < b; ++t) {
+            const int64_t i = g.tree_perm[t];
+            for (int c = 0; c < 3; ++c) g.xs[t * 3 + c] = c < d ? x[i * d + c] : 0.0;
+        }
+    });
+}
+
+// Max-heap of the best candidates by (D, slot).
+struct Candidates {
+    double dist[VECCHIA_KMAX];
+    int32_t slot[VECCHIA_KMAX];
+    int size = 0, cap = 0;
+
+    bool worse(int a, int b) const {  // entry a ranks after entry b
+        return dist[a] > dist[b] || (dist[a] == dist[b] && slot[a] > slot[b]);
+    }
+    bool full() const { return size == cap; }
+    double worst() const { return dist[0]; }
+    void offer(double dd, int32_t s) {
+        if (size < cap) {
+            int i = size++;
+            dist[i] = dd;
+            slot[i] = s;
+            while (i > 0) {
+                int p = (i - 1) / 2;
+                if (!worse(i, p)) break;
+                std::swap(dist[i], dist[p]);
+                std::swap(slot[i], slot[p]);
+                i = p;
+            }
+            return;
+        }
+        if (dd > dist[0] || (dd == dist[0] && s > slot[0])) return;
+        dist[0] = dd;
+        slot[0] = s;
+        int i = 0;
+        for (;;) {
+            int l = 2 * i + 1, r = l + 1, w = i;
+            if (l < size && worse(l, w)) w = l;
+            if (r < size && worse(r, w)) w = r;
+            if (w == i) break;
+            std::swap(dist[i], dist[w]);
+            std::swap(slot[i], slot[w]);
+            i = w;
+        }
+    }
+};
+
+inline double sqdist(const double* a, const double* b, int d) {
+    double dx = a[0] - b[0];
+    double acc = dx * dx;
+    if (d > 1) {
+        double dy = a[1] - b[1];
+        acc = acc + dy * dy;
+    }
+    if (d > 2) {
+        double dz = a[2] - b[2];
+        acc = acc + dz * dz;
+    }
+    return acc;
+}
+
+// The k nearest slots j < i of slot i (Sec. 2.1), written ascending by (D, j).
+void query_preceding(const vecchia_graph& g, int64_t i, int32_t* out) {
+    const double* q = &g.xs[i * 3];
+    const int d = g.d;
+    Candidates cand;
+    cand.cap = (int)std::min<int64_t>(g.k, i);
+    struct Item {
+        int64_t node;
+        double bound;
+    };
+    Item stack[192];
+    int sp = 0;
+    stack[sp++] = Item{0, 0.0};
+    while (sp > 0) {
+        const Item it = stack[--sp];
+        if (cand.full() && it.bound > cand.worst()) continue;
+        const int64_t t = it.node;
+        const double* p = &g.xs[t * 3];
+        cand.offer(sqdist(q, p, d), (int32_t)t);
+        const int s = g.sdim[t];
+        const double diff = q[s] - p[s];
+        const int64_t l = left_child(t), r = right_child(t);
+        const int64_t near_c = diff < 0.0 ? l : r, far_c = diff < 0.0 ? r : l;
+        const double plane = std::max(it.bound, diff * diff);
+        if (far_c < i && !(cand.full() && plane > cand.worst())) stack[sp++] = Item{far_c, plane};
+        if (near_c < i) stack[sp++] = Item{near_c, it.bound};
+    }
+    // heap -> ascending order
+    const int m = cand.size;
+    int32_t idx[VECCHIA_KMAX];
+    for (int a = 0; a < m; ++a) idx[a] = a;
+    std::sort(idx, idx + m, [&](int a, int b) {
+        return cand.dist[a] < cand.dist[b] || (cand.dist[a] == cand.dist[b] && cand.slot[a] < cand.slot[b]);
+    });
+    for (int a = 0; a < m; ++a) out[a] = cand.slot[idx[a]];
+    for (int a = m; a < g.k; ++a) out[a] = -1;
+}
+
+void build_neighbours(vecchia_graph& g, int nthreads) {
+    const int64_t ns = g.n - g.n0;
+    g.nbr.resize((size_t)ns * g.k);
+    parallel_for(ns, 2048, nthreads, [&](int64_t a, int64_t b) {
+        for (int64_t r = a; r < b; ++r) query_preceding(g, g.n0 + r, &g.nbr[(size_t)r * g.k]);
+    });
+}
+
+void build_depth(vecchia_graph& g) {
+    g.depth.assign(g.n, 0);
+    int32_t maxd = 0;
+    for (int64_t i = g.n0; i < g.n; ++i) {
+        const int32_t* row = &g.nbr[(size_t)(i - g.n0) * g.k];
+        int32_t dm = 0;
+        for (int m = 0; m < g.k; ++m) {
+            if (row[m] < 0) break;
+            dm = std::max(dm, g.depth[row[m]]);
+        }
+        g.depth[i] = dm + 1;
+        maxd = std::max(maxd, dm + 1);
+    }
+    g.n_levels = g.n > g.n0 ? maxd : 0;
+}
+
+void build_storage(vecchia_graph& g) {
+    const int64_t n = g.n;
+    const int L = g.n_levels;
+    std::vector<int64_t> count(L + 2, 0);
+    for (int64_t t = g.n0; t < n; ++t) count[g.depth[t]]++;
+    g.level_ptr.assign(L + 2, 0);
+    g.level_ptr[1] = g.n0;
+    for (int l = 1; l <= L; ++l) g.level_ptr[l + 1] = (int32_t)(g.level_ptr[l] + count[l]);
+    std::vector<int64_t> fill(L + 2);
+    for (int l = 1; l <= L; ++l) fill[l] = g.level_ptr[l];
+    g.order.assign(n, -1);
+    g.pos.assign(n, -1);
+    for (int64_t t = 0; t < g.n0; ++t) g.order[t] = (int32_t)t;
+    // in-order traversal of the tree: spatially coherent sequence of slots
+    std::vector<int64_t> stack;
+    stack.reserve(128);
+    int64_t t = 0;
+    while (t < n || !stack.empty()) {
+        while (t < n) {
+            stack.push_back(t);
+            t = left_child(t);
+        }
+        t = stack.back();
+        stack.pop_back();
+        if (t >= g.n0) g.order[fill[g.depth[t]]++] = (int32_t)t;
+        t = right_child(t);
+    }
+    for (int64_t s = 0; s < n; ++s) g.pos[g.order[s]] = (int32_t)s;
+}
+
+}  // namespace
+
+extern "C" int graph_build(const double* x, int64_t n, int32_t d, int32_t k, int32_t n0, int32_t n_threads,
+                           vecchia_graph** out) {
+    vecchia_clear_error();
+    if (!out) return vecchia_set_error(VECCHIA_EINVAL, "graph_build: out is NULL");
+    *out = nullptr;
+    if (!x) return vecchia_set_error(VECCHIA_EINVAL, "graph_build: x is NULL");
+    if (n < 1 || n >= (int64_t(1) << 31)) return vecchia_set_error(VECCHIA_EINVAL, "graph_build: need 1 <= N < 2^31, got %lld", (long long)n);
+    if (d < 1 || d > 3) return vecchia_set_error(VECCHIA_EINVAL, "graph_build: need 1 <= d <= 3, got %d", d);
+    if (k < 1 || k > VECCHIA_KMAX) return vecchia_set_error(VECCHIA_EINVAL, "graph_build: need 1 <= k <= %d, got %d", VECCHIA_KMAX, k);
+    if (n0 < 1 || n0 > n) return vecchia_set_error(VECCHIA_EINVAL, "graph_build: need 1 <= n0 <= N, got n0=%d", n0);
+    for (int64_t i = 0; i < n * d; ++i)
+        if (!std::isfinite(x[i])) return vecchia_set_error(VECCHIA_EINVAL, "graph_build: non-finite coordinate at point %lld", (long long)(i / d));
+    int nthreads = n_threads > 0 ? n_threads : (int)std::max(1u, std::thread::hardware_concurrency());
+    vecchia_graph* g = nullptr;
+    try {
+        g = new vecchia_graph();
+        g->n = n;
+        g->d = d;
+        g->k = k;
+        g->kp = vecchia_padded_k(k);
+        g->n0 = n0;
+        auto t0 = std::chrono::steady_clock::now();
+        build_tree(*g, x, nthreads);
+        g->times[0] = seconds_since(t0);
+        t0 = std::chrono::steady_clock::now();
+        build_neighbours(*g, nthreads);
+        g->times[1] = seconds_since(t0);
+        t0 = std::chrono::steady_clock::now();
+        build_depth(*g);
+        g->times[2] = seconds_since(t0);
+        t0 = std::chrono::steady_clock::now();
+        build_storage(*g);
+        g->times[3] = seconds_since(t0);
+    } catch (const std::bad_alloc&) {
+        delete g;
+        return vecchia_set_error(VECCHIA_ENOMEM, "graph_build: host allocation failed (N=%lld, k=%d)", (long long)n, k);
+    }
+    *out = g;
+    return VECCHIA_OK;
+}
+
+extern "C" int graph_info(const vecchia_graph* g, int64_t* n, int32_t* d, int32_t* k, int32_t* kp, int32_t* n0,
+                          int32_t* n_levels) {
+    if (!g) return vecchia_set_error(VECCHIA_EINVAL, "graph_info: graph is NULL");
+    if (n) *n = g->n;
+    if (d) *d = g->d;
+    if (k) *k = g->k;
+    if (kp) *kp = g->kp;
+    if (n0) *n0 = g->n0;
+    if (n_levels) *n_levels = g->n_levels;
+    return VECCHIA_OK;
+}
+
+extern "C" int graph_export(const vecchia_graph* g, int32_t* order, int32_t* slot, int32_t* level_ptr,
+                            int32_t* depth) {
+    if (!g) return vecchia_set_error(VECCHIA_EINVAL, "graph_export: graph is NULL");
+    for (int64_t s = 0; s < g->n; ++s) {
+        const int32_t t = g->order[s];
+        if (order) order[s] = g->tree_perm[t];
+        if (slot) slot[s] = t;
+        if (depth) depth[s] = g->depth[t];
+    }
+    if (level_ptr) std::memcpy(level_ptr, g->level_ptr.data(), sizeof(int32_t) * g->level_ptr.size());
+    return VECCHIA_OK;
+}
+
+extern "C" int graph_export_nbr(const vecchia_graph* g, int32_t layout, int32_t* nbr) {
+    if (!g || !nbr) return vecchia_set_error(VECCHIA_EINVAL, "graph_export_nbr: NULL argument");
+    if (layout != 0 && layout != 1) return vecchia_set_error(VECCHIA_EINVAL, "graph_export_nbr: layout must be 0 or 1");
+    const int64_t ns = g->n - g->n0;
+    const int k = g->k, kp = g->kp;
+    if (layout == 0) {
+        for (int64_t sp = 0; sp < ns; ++sp) {
+            const int32_t t = g->order[g->n0 + sp];
+            const int32_t* row = &g->nbr[(size_t)(t - g->n0) * k];
+            for (int m = 0; m < k; ++m) nbr[sp * k + m] = row[m] >= 0 ? g->pos[row[m]] : -1;
+        }
+        return VECCHIA_OK;
+    }
+    const int64_t tiles = (ns + 63) / 64;
+    for (int64_t tile = 0; tile < tiles; ++tile)
+        for (int m = 0; m < kp; ++m)
+            for (int lane = 0; lane < 64; ++lane) {
+                const int64_t sp = tile * 64 + lane;
+                int32_t v = -1;
+                if (sp < ns && m < k) {
+                    const int32_t t = g->order[g->n0 + sp];
+                    const int32_t j = g->nbr[(size_t)(t - g->n0) * k + m];
+                    v = j >= 0 ? g->pos[j] : -1;
+                }
+                nbr[(tile * kp + m) * 64 + lane] = v;
+            }
+    return VECCHIA_OK;
+}
+
+extern "C" int graph_export_points(const vecchia_graph* g, int32_t precision, void* xs) {
+    if (!g || !xs) return vecchia_set_error(VECCHIA_EINVAL, "graph_export_points: NULL argument");
+    if (precision != VECCHIA_FP64 && precision != VECCHIA_FP32)
+        return vecchia_set_error(VECCHIA_EINVAL, "graph_export_points: bad precision %d", precision);
+    for (int64_t s = 0; s < g->n; ++s) {
+        const double* p = &g->xs[(size_t)g->order[s] * 3];
+        for (int c = 0; c < 3; ++c) {
+            if (precision == VECCHIA_FP64)
+                static_cast<double*>(xs)[s * 3 + c] = p[c];
+            else
+                static_cast<float*>(xs)[s * 3 + c] = (float)p[c];
+        }
+    }
+    return VECCHIA_OK;
+}
+
+extern "C" int graph_export_children(const vecchia_graph* g, int64_t* child_ptr, int32_t* child) {
+    if (!g || !child_ptr || !child) return vecchia_set_error(VECCHIA_EINVAL, "graph_export_children: NULL argument");
+    const int64_t ns = g->n - g->n0;
+    if (ns * g->kp >= (int64_t(1) << 31))
+        return vecchia_set_error(VECCHIA_EUNSUPPORTED, "graph_export_children: Ns*kp = %lld does not fit int32", (long long)(ns * g->kp));
+    std::vector<int64_t> cnt(g->n + 1, 0);
+    for (int64_t sp = 0; sp < ns; ++sp) {
+        const int32_t t = g->order[g->n0 + sp];
+        const int32_t* row = &g->nbr[(size_t)(t - g->n0) * g->k];
+        for (int m = 0; m < g->k; ++m)
+            if (row[m] >= 0) cnt[g->pos[row[m]] + 1]++;
+    }
+    for (int64_t j = 0; j < g->n; ++j) cnt[j + 1] += cnt[j];
+    std::memcpy(child_ptr, cnt.data(), sizeof(int64_t) * (g->n + 1));
+    for (int64_t sp = 0; sp < ns; ++sp) {
+        const int32_t t = g->order[g->n0 + sp];
+        const int32_t* row = &g->nbr[(size_t)(t - g->n0) * g->k];
+        for (int m = 0; m < g->k; ++m)
+            if (row[m] >= 0) child[cnt[g->pos[row[m]]]++] = (int32_t)(sp * g->kp + m);
+    }
+    return VECCHIA_OK;
+}
+
+extern "C" int graph_build_times(const vecchia_graph* g, double* times) {
+    if (!g || !times) return vecchia_set_error(VECCHIA_EINVAL, "graph_build_times: NULL argument");
+    for (int i = 0; i < 4; ++i) times[i] = g->times[i];
+    return VECCHIA_OK;
+}
+
+extern "C" void graph_free(vecchia_graph* g) { delete g; }

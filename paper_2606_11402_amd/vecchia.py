@@ -1,0 +1,273 @@
+"""Python face of the native Vecchia library: marshalling only.
+
+``Graph`` wraps the host graph build (C++), ``DeviceGraph`` holds its arrays
+in HBM as torch tensors, and ``Factor`` owns one factor workspace and calls
+``vecchia_factor``/``vecchia_forward``/``vecchia_inverse``/``vecchia_logdet``
+on the current torch stream.  Every array the library sees is a caller-owned
+tensor; the library allocates nothing on the device.
+"""
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib
+
+EXP, M32, SE = _lib.EXP, _lib.M32, _lib.SE
+FP64, FP32 = _lib.FP64, _lib.FP32
+_TORCH_DTYPE = {FP64: torch.float64, FP32: torch.float32}
+_NP_DTYPE = {FP64: np.float64, FP32: np.float32}
+
+
+@dataclass(frozen=True)
+class KernelParams:
+    """Stationary covariance: kind EXP/M32/SE, amplitude sigma, length scale
+    ell and an absolute nugget on the diagonal."""
+    kind: int
+    sigma: float = 1.0
+    ell: float = 1.0
+    nugget: float = 0.0
+
+    def to_c(self):
+        return _lib.KernelStruct(int(self.kind), float(self.sigma), float(self.ell), float(self.nugget))
+
+
+def _ptr(a):
+    return ctypes.c_void_p(a.ctypes.data) if isinstance(a, np.ndarray) else ctypes.c_void_p(a.data_ptr())
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Graph:
+    """Bit-reversed k-d tree order, preceding k-NN and depth batches of a
+    point cloud, built on the host by the native library."""
+
+    def __init__(self, x, k, n0, n_threads=0):
+        x = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+        if x.ndim == 1:
+            x = x[:, None]
+        if x.ndim != 2:
+            raise ValueError("points must be (N, d)")
+        self._lib = _lib.load()
+        handle = ctypes.c_void_p()
+        _lib.check(self._lib.graph_build(x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), x.shape[0], x.shape[1],
+                                         int(k), int(n0), int(n_threads), ctypes.byref(handle)), "graph_build")
+        self._h = handle
+        n, d, kk, kp, nn0, nl = (ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(),
+                                 ctypes.c_int32(), ctypes.c_int32())
+        _lib.check(self._lib.graph_info(self._h, ctypes.byref(n), ctypes.byref(d), ctypes.byref(kk),
+                                        ctypes.byref(kp), ctypes.byref(nn0), ctypes.byref(nl)), "graph_info")
+        self.n, self.d, self.k, self.kp, self.n0, self.n_levels = (n.value, d.value, kk.value, kp.value,
+                                                                   nn0.value, nl.value)
+        self.order = np.empty(self.n, np.int32)
+        self.slot = np.empty(self.n, np.int32)
+        self.depth = np.empty(self.n, np.int32)
+        self.level_ptr = np.empty(self.n_levels + 2, np.int32)
+        _lib.check(self._lib.graph_export(self._h, _ptr(self.order), _ptr(self.slot), _ptr(self.level_ptr),
+                                          _ptr(self.depth)), "graph_export")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.graph_free(h)
+            self._h = None
+
+    @property
+    def ns(self):
+        return self.n - self.n0
+
+    @property
+    def ntiles(self):
+        return (self.ns + 63) // 64
+
+    def nbr(self, layout=0):
+        size = self.ns * self.k if layout == 0 else self.ntiles * self.kp * 64
+        out = np.empty(max(size, 1), np.int32)
+        _lib.check(self._lib.graph_export_nbr(self._h, layout, _ptr(out)), "graph_export_nbr")
+        return out[:size].reshape(self.ns, self.k) if layout == 0 else out[:size]
+
+    def points(self, precision=FP64):
+        out = np.empty((self.n, 3), _NP_DTYPE[precision])
+        _lib.check(self._lib.graph_export_points(self._h, precision, _ptr(out)), "graph_export_points")
+        return out
+
+    def children(self):
+        ptr = np.empty(self.n + 1, np.int64)
+        child = np.empty(max(self.ns * self.k, 1), np.int32)
+        _lib.check(self._lib.graph_export_children(self._h, _ptr(ptr), _ptr(child)), "graph_export_children")
+        return ptr, child[:ptr[-1]]
+
+    def build_times(self):
+        t = (ctypes.c_double * 4)()
+        _lib.check(self._lib.graph_build_times(self._h, t), "graph_build_times")
+        return {"tree": t[0], "neighbours": t[1], "depth": t[2], "storage": t[3]}
+
+    def to_device(self, precision=FP64, device="cuda", with_children=False):
+        return DeviceGraph(self, precision, device, with_children)
+
+    # storage <-> input order helpers (host)
+    def to_storage(self, values):
+        return np.asarray(values)[self.order]
+
+    def from_storage(self, values):
+        out = np.empty_like(np.asarray(values))
+        out[self.order] = values
+        return out
+
+
+class DeviceGraph:
+    """Graph arrays in HBM: coordinates in storage order (N x 3), tiled
+    neighbour indices, optional children lists; batch boundaries on the host."""
+
+    def __init__(self, g, precision, device, with_children=False):
+        self.n, self.k, self.kp, self.n0, self.n_levels = g.n, g.k, g.kp, g.n0, g.n_levels
+        self.precision = precision
+        self.device = torch.device(device)
+        self.level_ptr = np.ascontiguousarray(g.level_ptr, dtype=np.int32)
+        self.x = torch.from_numpy(g.points(precision)).to(self.device)
+        nbr = g.nbr(layout=1)
+        self.nbr = torch.from_numpy(nbr if nbr.size else np.full(1, -1, np.int32)).to(self.device)
+        self.child_ptr = self.child = None
+        if with_children:
+            ptr, child = g.children()
+            self.child_ptr = torch.from_numpy(ptr).to(self.device)
+            self.child = torch.from_numpy(child if child.size else np.zeros(1, np.int32)).to(self.device)
+
+    @property
+    def dtype(self):
+        return _TORCH_DTYPE[self.precision]
+
+
+def workspace_bytes(n, k, n0, precision):
+    out = ctypes.c_size_t()
+    _lib.check(_lib.load().vecchia_workspace_bytes(n, k, n0, precision, ctypes.byref(out)), "vecchia_workspace_bytes")
+    return out.value
+
+
+class Factor:
+    """One factored point set: b, sigma, L0 and logdet partials in a
+    device workspace, produced by ``vecchia_factor`` on the current stream."""
+
+    def __init__(self, dg, kernel, workspace=None):
+        self._lib = _lib.load()
+        self.dg = dg
+        self.kernel = kernel
+        nbytes = workspace_bytes(dg.n, dg.k, dg.n0, dg.precision)
+        if workspace is None:
+            workspace = torch.empty(nbytes, dtype=torch.uint8, device=dg.device)
+        if workspace.numel() < nbytes or workspace.data_ptr() % 256:
+            raise ValueError("workspace must hold %d bytes, 256-byte aligned" % nbytes)
+        self.workspace = workspace
+        v = _lib.ViewStruct()
+        v.n, v.k, v.kp, v.n0, v.n_levels, v.precision = dg.n, dg.k, dg.kp, dg.n0, dg.n_levels, dg.precision
+        v.x = dg.x.data_ptr()
+        v.nbr = dg.nbr.data_ptr()
+        v.level_ptr = dg.level_ptr.ctypes.data
+        v.child_ptr = dg.child_ptr.data_ptr() if dg.child_ptr is not None else None
+        v.child = dg.child.data_ptr() if dg.child is not None else None
+        v.workspace = workspace.data_ptr()
+        v.workspace_bytes = workspace.numel()
+        self.view = v
+        self._kc = kernel.to_c()
+        _lib.check(self._lib.vecchia_factor(ctypes.byref(self.view), ctypes.byref(self._kc), _stream(dg.device)),
+                   "vecchia_factor")
+
+    def _vec(self, t, name):
+        if not isinstance(t, torch.Tensor) or t.device != self.dg.device or t.dtype != self.dg.dtype \
+                or t.numel() != self.dg.n or not t.is_contiguous():
+            raise ValueError("%s must be a contiguous %s tensor of %d elements on %s"
+                             % (name, self.dg.dtype, self.dg.n, self.dg.device))
+        return t
+
+    def _out(self, out):
+        if out is None:
+            return torch.empty(self.dg.n, dtype=self.dg.dtype, device=self.dg.device)
+        return self._vec(out, "out")
+
+    def forward(self, xi, out=None):
+        """v = F(xi), both in storage order."""
+        xi = self._vec(xi, "xi")
+        v = self._out(out)
+        _lib.check(self._lib.vecchia_forward(ctypes.byref(self.view), ctypes.c_void_p(xi.data_ptr()),
+                                             ctypes.c_void_p(v.data_ptr()), _stream(self.dg.device)),
+                   "vecchia_forward")
+        return v
+
+    def inverse(self, v, out=None):
+        """xi = F^-1(v), both in storage order."""
+        v = self._vec(v, "v")
+        xi = self._out(out)
+        _lib.check(self._lib.vecchia_inverse(ctypes.byref(self.view), ctypes.c_void_p(v.data_ptr()),
+                                             ctypes.c_void_p(xi.data_ptr()), _stream(self.dg.device)),
+                   "vecchia_inverse")
+        return xi
+
+    def logdet(self, out=None):
+        """log det of the Vecchia covariance, as a 1-element float64 device tensor."""
+        if out is None:
+            out = torch.empty(1, dtype=torch.float64, device=self.dg.device)
+        _lib.check(self._lib.vecchia_logdet(ctypes.byref(self.view), ctypes.c_void_p(out.data_ptr()),
+                                            _stream(self.dg.device)), "vecchia_logdet")
+        return out
+
+    def status(self):
+        """Synchronise and raise VecchiaError(ENOTPD) if a pivot failed."""
+        bad = ctypes.c_int64()
+        _lib.check(self._lib.vecchia_status(ctypes.byref(self.view), _stream(self.dg.device), ctypes.byref(bad)),
+                   "vecchia_status")
+        return None
+
+    def first_bad_slot(self):
+        bad = ctypes.c_int64()
+        rc = self._lib.vecchia_status(ctypes.byref(self.view), _stream(self.dg.device), ctypes.byref(bad))
+        if rc not in (_lib.OK, _lib.ENOTPD):
+            _lib.check(rc, "vecchia_status")
+        return bad.value
+
+    def _ws_slice(self, name):
+        """Read-only views of the factor arrays (tests and diagnostics)."""
+        lay = _layout(self.dg)
+        esz = 8 if self.dg.precision == FP64 else 4
+        dt = self.dg.dtype
+        ws = self.workspace
+        if name == "b":
+            nb = self.dg_ntiles() * self.dg.kp * 64
+            return ws[lay["b"]:lay["b"] + nb * esz].view(dt)
+        if name == "sigma":
+            return ws[lay["sigma"]:lay["sigma"] + self.dg_ntiles() * 64 * esz].view(dt)
+        if name == "L0":
+            n0 = self.dg.n0
+            return ws[lay["l0"]:lay["l0"] + n0 * n0 * 8].view(torch.float64).view(n0, n0)
+        raise KeyError(name)
+
+    def dg_ntiles(self):
+        return (self.dg.n - self.dg.n0 + 63) // 64
+
+    def coefficients(self):
+        """(b as (Ns, kp) in sparse-index order, sigma (Ns,)) copied to the host."""
+        nt, kp, ns = self.dg_ntiles(), self.dg.kp, self.dg.n - self.dg.n0
+        b = self._ws_slice("b").cpu().numpy().reshape(nt, kp, 64).transpose(0, 2, 1).reshape(nt * 64, kp)[:ns]
+        s = self._ws_slice("sigma").cpu().numpy()[:ns]
+        return b, s
+
+
+def _align(x):
+    return (x + 255) & ~255
+
+
+def _layout(dg):
+    """Byte offsets of the workspace regions; mirrors the library's layout
+    (checked against vecchia_workspace_bytes in the tests)."""
+    ns = dg.n - dg.n0
+    ntiles = (ns + 63) // 64
+    esz = 8 if dg.precision == FP64 else 4
+    off = 0
+    lay = {"b": off}
+    off = _align(off + ntiles * dg.kp * 64 * esz)
+    lay["sigma"] = off
+    off = _align(off + ntiles * 64 * esz)
+    lay["l0"] = off
+    return lay

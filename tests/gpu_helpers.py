@@ -1,0 +1,65 @@
+"""Shared helpers of the GPU parity tests: run the HIP path through the C ABI
+and map its storage-order results to the oracle's slot order."""
+import numpy as np
+import torch
+
+import oracle
+from paper_2606_11402_amd import FP32, FP64, Factor, Graph, KernelParams
+
+
+def rel_err(a, ref):
+    """max |a - ref| / max |ref| (vectors), |a - ref| / |ref| (scalars)."""
+    a, ref = np.asarray(a, dtype=np.float64), np.asarray(ref, dtype=np.float64)
+    den = np.max(np.abs(ref)) if ref.size else 1.0
+    return float(np.max(np.abs(a - ref)) / den) if ref.size else 0.0
+
+
+class Run:
+    """Build the graph, upload, factor, forward(xi), inverse(v) on the GPU."""
+
+    def __init__(self, x, k, n0, kern, precision, xi_input=None, device="cuda:0"):
+        self.g = Graph(x, k, n0)
+        self.kern = kern
+        self.precision = precision
+        self.dg = self.g.to_device(precision, device)
+        self.fac = Factor(self.dg, KernelParams(kern.kind, kern.sigma, kern.ell, kern.nugget))
+        self.dtype = torch.float64 if precision == FP64 else torch.float32
+        self.xi_input = xi_input
+        if xi_input is not None:
+            xi_s = torch.from_numpy(self.g.to_storage(xi_input)).to(self.dtype).to(device)
+            self.v = self.fac.forward(xi_s)
+            self.xi_back = self.fac.inverse(self.v)
+        self.ld = self.fac.logdet()
+        torch.cuda.synchronize()
+
+    # storage <-> slot
+    def slot_order(self, storage_values):
+        out = np.empty_like(storage_values)
+        out[self.g.slot] = storage_values
+        return out
+
+    def coefficients_by_slot(self):
+        """(b rows, sigma) for sparse slots n0.. in slot order."""
+        b, s = self.fac.coefficients()
+        n0 = self.g.n0
+        rows = self.g.slot[n0:] - n0
+        bo = np.empty((self.g.ns, self.g.kp))
+        so = np.empty(self.g.ns)
+        bo[rows] = b
+        so[rows] = s
+        return bo[:, :self.g.k], so
+
+
+def oracle_run(x, k, n0, kern, xi_input=None):
+    og = oracle.build_graph(x, k, n0)
+    fac = oracle.factor(og, kern)
+    out = {"graph": og, "fac": fac, "logdet": oracle.logdet(fac)}
+    if xi_input is not None:
+        xi = np.asarray(xi_input)[og.perm]
+        out["xi"] = xi
+        out["v"] = oracle.forward(og, fac, xi)
+    return out
+
+
+def precision_of(name):
+    return FP64 if name == "fp64" else FP32

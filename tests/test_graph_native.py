@@ -1,0 +1,147 @@
+"""The C++ graph build (host, int32) against the oracle, bit for bit."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2606_11402_amd import Graph, VecchiaError
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def compare(x, k, n0, rows=None):
+    g = Graph(x, k, n0)
+    og = oracle.build_graph(x, k, n0) if rows is None else None
+    return g, og
+
+
+def assert_same_graph(g, og):
+    n0 = g.n0
+    assert (og.perm[g.slot] == g.order).all()
+    nb = g.nbr(0)
+    mapped = np.where(nb >= 0, g.slot[np.maximum(nb, 0)], -1)
+    assert (mapped == og.nbr[g.slot[n0:] - n0]).all()
+    assert (g.depth == og.depth[g.slot]).all()
+    assert g.n_levels == og.n_levels
+    assert g.slot[:n0].tolist() == list(range(n0))
+    for lev in range(1, g.n_levels + 1):
+        a, b = g.level_ptr[lev], g.level_ptr[lev + 1]
+        assert sorted(g.slot[a:b].tolist()) == og.level_slots(lev).tolist()
+
+
+def test_golden_1d():
+    t = json.load(open(os.path.join(GOLDEN, "tree_1d_n10.json")))
+    gj = json.load(open(os.path.join(GOLDEN, "graph_1d_n10.json")))
+    g = Graph(np.asarray(t["points_1d"], dtype=np.float64), gj["k"], gj["n0"])
+    assert g.order[np.argsort(g.slot)].tolist() == t["perm"]
+    nb = g.nbr(0)
+    rows = {int(g.slot[g.n0 + r]): [int(g.slot[j]) for j in nb[r]] for r in range(g.ns)}
+    assert [rows[s] for s in range(2, 10)] == gj["nbr_rows_for_slots_2_to_9"]
+
+
+@pytest.mark.parametrize("n,d,k,n0,seed", [
+    (3000, 3, 8, 32, 0), (2000, 2, 16, 16, 1), (1500, 1, 5, 3, 2), (4000, 3, 32, 32, 3),
+    (777, 3, 32, 1, 4),        # padded rows: n0 < k
+    (64, 3, 8, 64, 5),         # dense block only
+    (65, 3, 8, 64, 6),         # one sparse point
+])
+def test_bit_exact_against_oracle(n, d, k, n0, seed):
+    x = np.random.default_rng(seed).random((n, d))
+    g = Graph(x, k, n0)
+    assert_same_graph(g, oracle.build_graph(x, k, n0))
+
+
+def test_ties_integer_grid():
+    x = np.stack(np.meshgrid(*[np.arange(8)] * 3, indexing="ij"), -1).reshape(-1, 3).astype(np.float64)
+    g = Graph(x, 8, 8)
+    assert_same_graph(g, oracle.build_graph(x, 8, 8))
+
+
+def test_duplicates_and_dynamic_range():
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal((1500, 3)) * (10.0 ** rng.uniform(-3, 0, 1500))[:, None]
+    x[100:120] = x[5]
+    g = Graph(x, 16, 16)
+    assert_same_graph(g, oracle.build_graph(x, 16, 16))
+
+
+@pytest.mark.slow
+def test_sampled_rows_large():
+    """N = 2^16 radial cloud: the whole tree order and sampled neighbour rows
+    (first and last 512 rows plus 2048 random) against brute force."""
+    import workloads
+    x = workloads.as_fp32_exact(workloads.radial(1 << 16, 2))
+    k, n0 = 16, 128
+    g = Graph(x, k, n0)
+    perm, _ = oracle.tree_order(x)
+    assert (perm[g.slot] == g.order).all()
+    xs = x[perm]
+    nb = g.nbr(0)
+    pos = np.empty(g.n, np.int64)
+    pos[g.slot] = np.arange(g.n)
+    rng = np.random.default_rng(11)
+    slots = np.unique(np.concatenate([np.arange(n0, n0 + 512), np.arange(g.n - 512, g.n),
+                                      rng.integers(n0, g.n, 2048)]))
+    for s in slots:
+        ref = oracle.preceding_knn(xs[:s + 1], k, s)[0]
+        got = g.slot[nb[pos[s] - n0]]
+        assert (got == ref).all()
+
+
+def test_tiled_layout_matches_row_major():
+    x = np.random.default_rng(8).random((1000, 3))
+    g = Graph(x, 12, 41)                  # Ns = 959: ragged last tile
+    rm = g.nbr(0)
+    tl = g.nbr(1).reshape(g.ntiles, g.kp, 64)
+    for sp in (0, 1, 63, 64, 500, g.ns - 1):
+        row = tl[sp // 64, :, sp % 64]
+        assert row[:12].tolist() == rm[sp].tolist() and (row[12:] == -1).all()
+    assert (tl.reshape(g.ntiles, g.kp, 64)[-1, :, g.ns % 64:] == -1).all()
+
+
+def test_children_lists_invert_neighbours():
+    x = np.random.default_rng(9).random((800, 3))
+    g = Graph(x, 8, 16)
+    ptr, child = g.children()
+    nb = g.nbr(0)
+    seen = np.zeros_like(nb, dtype=bool)
+    for j in range(g.n):
+        entries = child[ptr[j]:ptr[j + 1]]
+        assert (np.diff(entries) > 0).all()
+        for e in entries:
+            sp, m = divmod(int(e), g.kp)
+            assert nb[sp, m] == j
+            seen[sp, m] = True
+    assert seen[nb >= 0].all()
+
+
+@pytest.mark.parametrize("args", [
+    dict(k=0, n0=4), dict(k=33, n0=40), dict(k=4, n0=0), dict(k=4, n0=2000),
+])
+def test_invalid_arguments(args):
+    x = np.random.default_rng(0).random((100, 3))
+    with pytest.raises(VecchiaError) as e:
+        Graph(x, args["k"], args["n0"])
+    assert e.value.code == -1
+
+
+def test_non_finite_rejected():
+    x = np.random.default_rng(0).random((100, 3))
+    x[50, 1] = np.nan
+    with pytest.raises(VecchiaError):
+        Graph(x, 4, 8)
+
+
+def test_storage_order_is_spatially_coherent_inside_levels():
+    """Inside a batch, points follow the tree's in-order sequence: consecutive
+    storage positions are much closer than random pairs."""
+    x = np.random.default_rng(10).random((20000, 3))
+    g = Graph(x, 8, 64)
+    xs = g.points()
+    a, b = g.level_ptr[g.n_levels // 2], g.level_ptr[g.n_levels // 2 + 1]
+    if b - a > 100:
+        consecutive = np.linalg.norm(np.diff(xs[a:b], axis=0), axis=1).mean()
+        rnd = np.linalg.norm(xs[a:b] - xs[np.random.default_rng(0).permutation(np.arange(a, b))], axis=1).mean()
+        assert consecutive < 0.5 * rnd
