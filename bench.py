@@ -1,0 +1,281 @@
+#!/usr/bin/env python3
+"""Throughput of the Vecchia hot path on one MI355X.
+
+One step = factor (Eq. (2) for every point + dense block) + forward
+(Alg. 1, batch by batch) + logdet, on the workload's point cloud resident in
+HBM.  The host graph build runs once before timing (it depends only on the
+points) and is reported separately.  Prints ONE JSON line on stdout; progress
+goes to stderr.
+
+Default workload: 2^26 points, 90% uniform in [0,1]^3 + 10% Gaussian clumps
+of width 1e-3, k = 32, squared-exponential kernel ell = 0.02, nugget 1e-6,
+FP32 storage with FP64 pivots and logdet.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+VALU_PEAK_TFLOPS = 78.6        # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz: FP32 unpacked = FP64 FMA rate
+METRIC = "points/sec Vecchia factor+forward+logdet (k=16,32); p50/p99 req latency"
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def eval_flops(kind):
+    # flops of one kernel evaluation from three coordinate differences:
+    # r^2 (3 sub, 3 mul, 2 add) + scaling and amplitude; exp and sqrt count 1 each
+    return {0: 12, 1: 14, 2: 11}[kind]
+
+
+def factor_flops_per_point(k, kind, refine):
+    """Algorithmic flops of Eq. (2) for one point with k neighbours."""
+    evals = k * (k + 1) // 2 + k                    # lower K_cc + k_ci
+    chol = k ** 3 / 3.0 + k * k / 2.0               # right-looking Cholesky
+    solves = 2.0 * k * k + 2 * k                    # L y = k_ci, L^T b = y, sigma^2
+    total = evals * eval_flops(kind) + chol + solves
+    if refine:
+        total += (k * (k + 1) // 2) * eval_flops(kind) + 2.0 * k * k   # residual k - K b
+        total += 2.0 * k * k + 2 * k                                   # correction solves, k.b
+    return total
+
+
+def apply_bytes_per_point(k, esz):
+    # neighbour index + coefficient + gathered v per neighbour, sigma, xi/v in, v/xi out
+    return 4 * k + esz * k + esz * k + 3 * esz
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", type=int, default=3)
+    ap.add_argument("--n", type=int, default=None, help="override N (default: the workload's)")
+    ap.add_argument("--k", type=int, default=None)
+    ap.add_argument("--threads", type=int, default=0, help="host threads for the graph build")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true", help="skip the sampled oracle check")
+    ap.add_argument("--cpu-sample", type=int, default=8192)
+    ap.add_argument("--cpu-passes", type=int, default=8)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures the Vecchia hot path on one GPU only; runs on several GPUs are not "
+              "part of this build (see DESIGN.md for how the path would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2606_11402_amd import FP32, FP64, Factor, Graph, KernelParams
+    from paper_2606_11402_amd import vecchia as vmod
+
+    w = workloads.WORKLOADS[args.workload]
+    n = args.n or w.n
+    k = args.k or w.k
+    n0 = w.n0
+    precision = FP32 if "fp32" in w.precisions else FP64
+    esz = 4 if precision == FP32 else 8
+    dev = torch.device("cuda:0")
+    kern = KernelParams(w.kind, w.sigma, w.ell, w.nugget)
+
+    log("workload %s: N=%d k=%d n0=%d, generating points" % (w.name, n, k, n0))
+    t = time.time()
+    x = w.points(n)
+    xi_in = w.xi(n)
+    log("points ready in %.1fs; building graph on the host" % (time.time() - t))
+    t = time.time()
+    g = Graph(x, k, n0, n_threads=args.threads)
+    graph_s = time.time() - t
+    log("graph: %.1fs %s, %d levels" % (graph_s, {a: round(b, 2) for a, b in g.build_times().items()}, g.n_levels))
+    t = time.time()
+    dg = g.to_device(precision, dev)
+    dt = dg.dtype
+    xi = torch.from_numpy(g.to_storage(xi_in)).to(dt).to(dev)
+    del x
+    v = torch.empty(n, dtype=dt, device=dev)
+    ld = torch.empty(1, dtype=torch.float64, device=dev)
+    fac = Factor(dg, kern)
+    fac.status()
+    n_bad, n_redo = fac.counts()
+    upload_s = time.time() - t
+    log("uploaded and factored once in %.1fs" % upload_s)
+
+    def step():
+        fac.refactor()
+        fac.forward(xi, out=v)
+        fac.logdet(out=ld)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    fac.status()
+
+    # ---- timed region: K whole steps, no per-kernel instrumentation
+    log("timing %d steps" % args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = n / (ms_per_step / 1e3)
+    log("%.3f ms/step, %.3e points/s" % (ms_per_step, value))
+
+    # ---- same steps with HIP events around every launch (per-kernel times)
+    vmod.profile_reset()
+    vmod.profile_enable(True)
+    torch.cuda.synchronize()
+    tp0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    inv_out = torch.empty_like(v)
+    for _ in range(args.steps):
+        fac.inverse(v, out=inv_out)
+    torch.cuda.synchronize()
+    tp1 = time.perf_counter()
+    prof = vmod.profile_read()
+    vmod.profile_enable(False)
+    log("per-kernel totals:", {a: (round(b[0], 3), b[1]) for a, b in prof.items()})
+
+    ns = n - n0
+    steps = args.steps
+    f_ms = prof["factor_sparse"][0] / prof["factor_sparse"][1]
+    flops = factor_flops_per_point(k, w.kind, precision == FP32) * ns
+    f_tflops = flops / (f_ms * 1e-3) / 1e12
+    fwd_ms = (prof["forward_level"][0] + prof.get("forward_dense", (0.0, 0))[0]) / steps
+    ld_ms = prof["logdet"][0] / prof["logdet"][1]
+    inv_ms = (prof["inverse_sparse"][0] + prof.get("inverse_dense", (0.0, 0))[0]) / steps
+    inv_sparse_ms = prof["inverse_sparse"][0] / prof["inverse_sparse"][1]
+    bpp = apply_bytes_per_point(k, esz)
+    fwd_gbs = bpp * ns / (fwd_ms * 1e-3) / 1e9
+    ldbytes = 8 * ((ns + 63) // 64)
+    fl_gbs = (bpp * ns + ldbytes) / ((fwd_ms + ld_ms) * 1e-3) / 1e9
+    inv_gbs = bpp * ns / (inv_sparse_ms * 1e-3) / 1e9
+    levels_ms = prof["forward_level"][0] / steps
+
+    roofline = {
+        "kernel": "factor_sparse (Eq. 2 per point: gather, K_cc, Cholesky, solves, refinement)",
+        "bound": "alu", "achieved": round(f_tflops, 3), "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+        "frac": round(f_tflops / VALU_PEAK_TFLOPS, 4), "traffic": None,
+        "flops_per_point": factor_flops_per_point(k, w.kind, precision == FP32), "points_per_launch": ns,
+        "avg_launch_ms": round(f_ms, 4),
+    }
+    others = {
+        "forward": {"bound": "hbm", "achieved": round(fwd_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(fwd_gbs / HBM_PEAK_GBS, 4), "bytes_per_point": bpp,
+                    "ms_per_forward": round(fwd_ms, 4), "launches_per_forward": g.n_levels + 1},
+        "forward+logdet": {"bound": "hbm", "achieved": round(fl_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": round(fl_gbs / HBM_PEAK_GBS, 4), "ms": round(fwd_ms + ld_ms, 4)},
+        "inverse_sparse": {"bound": "hbm", "achieved": round(inv_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": round(inv_gbs / HBM_PEAK_GBS, 4), "avg_launch_ms": round(inv_sparse_ms, 4)},
+    }
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "points/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32" if precision == FP32 else "f64", "data": "synthetic",
+        "config": {"workload": w.name, "n": n, "k": k, "n0": n0, "kernel": ["EXP", "M32", "SE"][w.kind],
+                   "ell": w.ell, "sigma": w.sigma, "nugget": w.nugget,
+                   "precision": "fp32 storage/arithmetic, fp64 pivots, variances and logdet" if precision == FP32
+                   else "fp64", "levels": g.n_levels, "points_recomputed_fp64": n_redo},
+        "roofline": roofline,
+        "rooflines_other": others,
+        "ops_ms": {"factor_sparse": round(f_ms, 4), "forward": round(fwd_ms, 4), "forward_levels_only": round(levels_ms, 4),
+                   "logdet": round(ld_ms, 4), "inverse": round(inv_ms, 4),
+                   "instrumented_step_ms": round((tp1 - tp0) * 1e3 / steps, 3)},
+        "graph_build_s": round(graph_s, 2), "graph_phases_s": {a: round(b, 2) for a, b in g.build_times().items()},
+    }
+
+    # ---- sampled check against the oracle at full size (outside the timed region)
+    if not args.no_check:
+        out["check"] = sampled_check(g, fac, v, xi, kern, w, n, k, n0)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, k, n0, args.cpu_sample, args.cpu_passes)
+    print(json.dumps(out), flush=True)
+
+
+def sampled_check(g, fac, v, xi, kern, w, n, k, n0, samples=256):
+    """Per-point checks the oracle can do one by one at any N: b and sigma of
+    sampled points from Eq. (2) in FP64, and the forward identity
+    v_i = b_i . v[c(i)] + sigma_i xi_i evaluated with the oracle's b, sigma on
+    the GPU's own v."""
+    import numpy as np
+
+    import oracle
+    rng = np.random.default_rng(12345)
+    rows = rng.choice(g.ns, size=min(samples, g.ns), replace=False)
+    xs = g.points()                                    # FP64 values of the FP32 coordinates
+    nb = g.nbr(0)[rows]
+    b_gpu, s_gpu = fac.coefficient_rows(rows)
+    vh = v.double().cpu().numpy()
+    xih = xi.double().cpu().numpy()
+    ok_kern = oracle.Kernel(kern.kind, kern.sigma, kern.ell, kern.nugget)
+    eb = es = ev = 0.0
+    bmax = smax = vmax = 0.0
+    for t, r in enumerate(rows):
+        c = nb[t][nb[t] >= 0]
+        b, s = oracle.conditional(xs[c], xs[n0 + r], ok_kern)
+        eb = max(eb, float(np.max(np.abs(b_gpu[t][:len(c)] - b))))
+        bmax = max(bmax, float(np.max(np.abs(b))))
+        es = max(es, abs(s_gpu[t] - s))
+        smax = max(smax, s)
+        vi = b @ vh[c] + s * xih[n0 + r]
+        ev = max(ev, abs(vh[n0 + r] - vi))
+        vmax = max(vmax, abs(vi))
+    return {"samples": int(len(rows)), "b_rel": float(eb / bmax), "sigma_rel": float(es / smax),
+            "forward_identity_rel": float(ev / vmax), "logdet": float(fac.logdet().item())}
+
+
+def cpu_baseline(w, k, n0, n_sample, passes):
+    """The FP64 oracle (as written, not tuned) on a sample of the same
+    workload: factor + forward + logdet, the graph built untimed."""
+    import numpy as np
+    import oracle
+    import workloads
+    try:
+        from threadpoolctl import threadpool_limits
+        limiter = threadpool_limits(1)
+    except Exception:
+        limiter = None
+    gen = {"uniform": workloads.uniform, "radial": workloads.radial, "clumped": workloads.clumped,
+           "gaussian": workloads.gaussian}[w.dist]
+    x = workloads.as_fp32_exact(gen(n_sample, w.number))
+    log("cpu baseline: oracle graph for N=%d (untimed)" % n_sample)
+    og = oracle.build_graph(x, k, n0)
+    kern = oracle.Kernel(w.kind, w.sigma, w.ell, w.nugget)
+    xi = workloads.white_noise(n_sample, w.number + 100)[og.perm]
+    t = time.perf_counter()
+    for _ in range(passes):
+        fac = oracle.factor(og, kern)
+        oracle.forward(og, fac, xi)
+        oracle.logdet(fac)
+    dt = time.perf_counter() - t
+    if limiter is not None:
+        limiter.unregister() if hasattr(limiter, "unregister") else None
+    cpu = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": passes * n_sample / dt, "unit": "points/s", "cores": 1, "kind": "oracle",
+            "sample": "same distribution, kernel and k at N=%d, %d passes of factor+forward+logdet "
+                      "(FP64 NumPy, one thread); graph built untimed" % (n_sample, passes),
+            "seconds": round(dt, 2), "host_cpu": cpu, "host_threads_available": os.cpu_count()}
+
+
+if __name__ == "__main__":
+    main()

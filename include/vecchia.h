@@ -138,7 +138,10 @@ typedef struct vecchia_view {
     int32_t n0;                /* dense block size */
     int32_t n_levels;          /* L */
     int32_t precision;         /* VECCHIA_FP64 or VECCHIA_FP32 */
-    int32_t reserved;
+    int32_t redo_log2;         /* VECCHIA_FP32: a point whose smallest Cholesky pivot is below
+                                  2^-redo_log2 * K_ii, or not positive, is recomputed entirely in
+                                  double (results stored as float).  0 = default (16); < 0 = only
+                                  points whose float factorisation fails.  Ignored for FP64. */
     const void* x;             /* (device) N x 3 coordinates in storage order, double or float */
     const int32_t* nbr;        /* (device) tiled neighbour indices (graph_export_nbr layout 1) */
     const int32_t* level_ptr;  /* (host)   L + 2 batch boundaries (graph_export) */
@@ -192,6 +195,11 @@ int vecchia_backward(const vecchia_view* view, const vecchia_kernel* kern,
                      const void* xi, const void* v, const void* v_bar, const void* xi_bar_in,
                      double logdet_bar, void* xi_bar, void* v_bar_out, double* theta_bar,
                      void* scratch, size_t scratch_bytes, void* stream);
+
+/* Synchronises `stream`, then reports how many points of the last
+ * vecchia_factor had a non-positive pivot or variance (not_pd) and, for
+ * VECCHIA_FP32, how many were recomputed in double (recomputed). */
+int vecchia_factor_counts(const vecchia_view* view, void* stream, int64_t* not_pd, int64_t* recomputed);
 
 /* Synchronises `stream`, then reads the workspace status word.  Returns
  * VECCHIA_OK, or VECCHIA_ENOTPD with *first_bad_slot = the smallest storage

@@ -37,7 +37,7 @@ class KernelStruct(ctypes.Structure):
 class ViewStruct(ctypes.Structure):
     _fields_ = [
         ("n", c_int64), ("k", c_int32), ("kp", c_int32), ("n0", c_int32), ("n_levels", c_int32),
-        ("precision", c_int32), ("reserved", c_int32),
+        ("precision", c_int32), ("redo_log2", c_int32),
         ("x", c_void_p), ("nbr", c_void_p), ("level_ptr", c_void_p), ("child_ptr", c_void_p),
         ("child", c_void_p), ("workspace", c_void_p), ("workspace_bytes", c_size_t),
         ("kernel", KernelStruct),
@@ -62,6 +62,7 @@ _SIGNATURES = {
     "vecchia_backward": (c_int32, [P(ViewStruct), P(KernelStruct), c_void_p, c_void_p, c_void_p, c_void_p,
                                    c_double, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "vecchia_status": (c_int32, [P(ViewStruct), c_void_p, P(c_int64)]),
+    "vecchia_factor_counts": (c_int32, [P(ViewStruct), c_void_p, P(c_int64), P(c_int64)]),
     "vecchia_padded_k": (c_int32, [c_int32]),
     "vecchia_profile_enable": (c_int32, [c_int32]),
     "vecchia_profile_read": (c_int32, [ctypes.c_char_p, c_size_t, P(c_double), P(c_int64), c_int32, P(c_int32)]),

@@ -1,0 +1,421 @@
+// Reverse-mode derivatives of forward, inverse and logdet (Sec. 2.3: forward
+// and backward derivatives with respect to the kernel parameters).
+//
+// With F = (I - B)^-1 D (B strictly lower, row i = b_i at the columns c(i);
+// D = diag(sigma); the dense block folded in as (I - B0)^-1 D0 = L0):
+//   forward  v = F xi, cotangent vbar:  w = (I - B)^-T vbar by a reverse
+//            sweep over the batches (children lists, a gather: deterministic),
+//            xibar_i = sigma_i w_i, xibar0 = L0^T w0;
+//   inverse  xi = F^-1 v, cotangent xibar: z = xibar / sigma,
+//            vbar = (I - B)^T z, plus L0^-T xibar0 on the dense block;
+//   logdet   cotangent ldbar: sigma_bar_i += 2 ldbar / sigma_i, K0bar += ldbar K0^-1.
+// Per sparse point, with omega_i = w_i - z_i, bbar_i = omega_i v[c(i)],
+// sigma_bar_i = omega_i xi_i + 2 ldbar/sigma_i, sbar = sigma_bar_i/(2 sigma_i)
+// and u = K_cc^-1 bbar (K_cc and its Cholesky factor recomputed, nothing of
+// size k^2 stored):
+//   theta_bar += sbar dK_ii + sum_p (u_p - 2 sbar b_p) dk_p
+//                + sum_{p,q} (sbar b_p - u_p) b_q dK_pq        (theta = sigma, ell)
+// The dense block uses the Cholesky adjoint: with gamma = w0 - L0^-T xibar0,
+// h = L0^T gamma, M = Phi(h xi0^T) + ldbar I (lower triangle, diagonal
+// halved), theta_bar += sum_pq (L0^-T M L0^-1)_pq dK0_pq.
+// All theta sums are accumulated in double and reduced in a fixed order.
+#include <algorithm>
+
+#include "factor_kernel.h"
+
+namespace vk {
+
+// kappa(r) and d kappa / d ell (no nugget), double.
+template <int KIND>
+__device__ __forceinline__ void cov_and_dell(double r2, const Cov<double>& c, double& kap, double& dell) {
+    if constexpr (KIND == 0) {
+        const double r = sqrt(r2);
+        kap = c.s2 * exp(-r * c.inv_ell);
+        dell = kap * r * c.inv_ell * c.inv_ell;
+    } else if constexpr (KIND == 1) {
+        const double a = sqrt(r2) * c.c_m32;
+        const double e = exp(-a);
+        kap = c.s2 * (1.0 + a) * e;
+        dell = c.s2 * a * a * e * c.inv_ell;
+    } else {
+        kap = c.s2 * exp(r2 * c.c_se);
+        dell = kap * r2 * c.inv_ell * c.inv_ell * c.inv_ell;
+    }
+}
+
+template <typename TS>
+struct AdjArgs {
+    const TS* x;
+    const int32_t* nbr;
+    const int64_t* child_ptr;
+    const int32_t* child;
+    const TS* b;
+    const TS* sigma;
+    const double* l0;
+    const TS* xi;           // the pair (xi, v)
+    const TS* v;
+    const TS* vbar;         // may be null
+    const TS* xibar_in;     // may be null
+    TS* w;                  // scratch, N
+    TS* xibar;              // output (forward part)
+    TS* vbar_out;           // output (inverse part)
+    double* t0;             // scratch, n0: L0^-T xibar0
+    double* theta_part;     // scratch, 2 per block of the theta kernel
+    double* theta_dense;    // scratch, 2
+    double* theta_out;      // output, 2
+    int64_t n, ns, nblocks;
+    int n0, kp;
+    double ldbar;
+    double sigma_amp;
+    double diag;            // K_ii = sigma^2 + nugget
+    Cov<double> cov;
+};
+
+// ---- reverse sweep of one batch: w_j = vbar_j + sum_children b w_child
+template <typename TS, int KP>
+__global__ __launch_bounds__(kBlock) void adj_sweep_kernel(AdjArgs<TS> a, int64_t j_begin, int64_t j_end) {
+    constexpr int SH = KP == 8 ? 3 : (KP == 16 ? 4 : 5);
+    const int64_t j = j_begin + (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j >= j_end) return;
+    double acc = (double)a.vbar[j];
+    for (int64_t e = a.child_ptr[j]; e < a.child_ptr[j + 1]; ++e) {
+        const int32_t packed = a.child[e];
+        const int64_t sp = packed >> SH;
+        const int m = packed & (KP - 1);
+        acc = fma((double)a.b[((sp >> 6) * KP + m) * kTile + (sp & 63)], (double)a.w[a.n0 + sp], acc);
+    }
+    a.w[j] = (TS)acc;
+    if (j >= a.n0) a.xibar[j] = (TS)((double)a.sigma[j - a.n0] * acc);
+}
+
+// ---- inverse part: vbar_j = z_j - sum_children b z_child, z = xibar / sigma
+template <typename TS, int KP>
+__global__ __launch_bounds__(kBlock) void adj_inverse_kernel(AdjArgs<TS> a) {
+    constexpr int SH = KP == 8 ? 3 : (KP == 16 ? 4 : 5);
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j >= a.n) return;
+    double acc = j >= a.n0 ? (double)a.xibar_in[j] / (double)a.sigma[j - a.n0] : 0.0;
+    for (int64_t e = a.child_ptr[j]; e < a.child_ptr[j + 1]; ++e) {
+        const int32_t packed = a.child[e];
+        const int64_t sp = packed >> SH;
+        const int m = packed & (KP - 1);
+        const double z = (double)a.xibar_in[a.n0 + sp] / (double)a.sigma[sp];
+        acc = fma(-(double)a.b[((sp >> 6) * KP + m) * kTile + (sp & 63)], z, acc);
+    }
+    a.vbar_out[j] = (TS)acc;
+}
+
+// ---- dense block, inverse part: t0 = L0^-T xibar0, vbar_out[0:n0] += t0
+template <typename TS>
+__global__ __launch_bounds__(VECCHIA_N0MAX) void adj_dense_inverse_kernel(AdjArgs<TS> a) {
+    __shared__ double t[VECCHIA_N0MAX];
+    const int i = threadIdx.x;
+    const int n0 = a.n0;
+    double ri = i < n0 ? (double)a.xibar_in[i] : 0.0;
+    for (int j = n0 - 1; j >= 0; --j) {
+        if (i == j) t[j] = ri / a.l0[j * n0 + j];
+        __syncthreads();
+        if (i < j) ri = fma(-a.l0[j * n0 + i], t[j], ri);
+    }
+    if (i < n0) {
+        a.t0[i] = t[i];
+        a.vbar_out[i] = (TS)((double)a.vbar_out[i] + t[i]);
+    }
+}
+
+__device__ __forceinline__ void block_sum2(double& s0, double& s1, double* sh) {
+    for (int off = 32; off > 0; off >>= 1) {
+        s0 += __shfl_xor(s0, off, 64);
+        s1 += __shfl_xor(s1, off, 64);
+    }
+    const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sh[2 * wv] = s0;
+        sh[2 * wv + 1] = s1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a0 = 0.0, a1 = 0.0;
+        for (int w = 0; w < nw; ++w) {
+            a0 += sh[2 * w];
+            a1 += sh[2 * w + 1];
+        }
+        s0 = a0;
+        s1 = a1;
+    }
+}
+
+// ---- per sparse point: theta contributions (double throughout)
+template <typename TS, int K, int KIND>
+__global__ __launch_bounds__(kBlock) void adj_theta_kernel(AdjArgs<TS> a) {
+    constexpr int P = factor_lanes(VECCHIA_FP64, K);
+    constexpr int R = K / P;
+    constexpr int NA = P * R * (R + 1) / 2;
+    constexpr int PTS = kBlock / P;
+    const int tid = threadIdx.x;
+    const int r = tid % P;
+    const int64_t sp_raw = (int64_t)blockIdx.x * PTS + tid / P;
+    const bool live = sp_raw < a.ns;
+    const int64_t sp = live ? sp_raw : a.ns - 1;
+    const int64_t base = (sp >> 6) * (int64_t)K * kTile + (sp & 63);
+    const int64_t s = a.n0 + sp;
+
+    const double sig = (double)a.sigma[sp];
+    double omega = a.vbar ? (double)a.w[s] : 0.0;
+    if (a.xibar_in) omega -= (double)a.xibar_in[s] / sig;
+    const double sigma_bar = omega * (double)a.xi[s] + 2.0 * a.ldbar / sig;
+    const double sbar = sigma_bar / (2.0 * sig);
+
+    double c0[R], c1[R], c2[R];
+    int ok[R];
+    gather_rows<double, TS, K, P>(a.x, a.nbr, base, r, c0, c1, c2, ok);
+    double bq[R], bbar[R];
+    static_for<0, R>([&](auto PI) {
+        constexpr int p = PI;
+        const int32_t j = a.nbr[base + (int64_t)(p * P + r) * kTile];
+        bq[p] = (double)a.b[base + (int64_t)(p * P + r) * kTile];
+        bbar[p] = j >= 0 ? omega * (double)a.v[j] : 0.0;
+    });
+
+    double A[NA];
+    assemble_kcc<double, K, P, KIND>(c0, c1, c2, ok, r, a.cov, A);
+    double Dg[R];
+    static_for<0, R>([&](auto PI) {
+        constexpr int p = PI;
+        Dg[p] = ok[p] ? a.diag : 1.0;
+    });
+    double Inv[R];
+    bool bad = false;
+    double minpiv = 1.0;
+    cholesky_kcc<double, K, P>(A, Dg, Inv, r, bad, minpiv);
+    double u[R];
+    static_for<0, R>([&](auto PI) { u[(int)PI] = bbar[(int)PI]; });
+    lower_solve<double, K, P>(A, Inv, u, r);
+    upper_solve<double, K, P>(A, Inv, u, r);
+
+    const TS* xt = a.x + s * 3;
+    const double t0 = (double)xt[0], t1 = (double)xt[1], t2 = (double)xt[2];
+    const double inv_amp = 1.0 / a.sigma_amp;
+    double acc_s = 0.0, acc_l = 0.0;
+    static_for<0, R>([&](auto PI) {
+        constexpr int p = PI;
+        double kap, dl;
+        cov_and_dell<KIND>(sqdist3(c0[p], c1[p], c2[p], t0, t1, t2), a.cov, kap, dl);
+        const double coef = ok[p] ? (u[p] - 2.0 * sbar * bq[p]) : 0.0;
+        acc_s = fma(coef, 2.0 * kap * inv_amp, acc_s);
+        acc_l = fma(coef, dl, acc_l);
+    });
+    static_for<0, K>([&](auto QI) {
+        constexpr int q = QI, pq = q / P, rq = q % P;
+        const double y0 = group_bcast<P, rq>(c0[pq]);
+        const double y1 = group_bcast<P, rq>(c1[pq]);
+        const double y2 = group_bcast<P, rq>(c2[pq]);
+        const int okq = group_bcast<P, rq>(ok[pq]);
+        const double bqq = group_bcast<P, rq>(bq[pq]);
+        static_for<0, R>([&](auto PI) {
+            constexpr int p = PI;
+            double kap, dl;
+            cov_and_dell<KIND>(sqdist3(c0[p], c1[p], c2[p], y0, y1, y2), a.cov, kap, dl);
+            const bool both = (ok[p] & okq) != 0;
+            const bool same = (p * P + r) == q;
+            const double ds = both ? (same ? 2.0 * a.sigma_amp : 2.0 * kap * inv_amp) : 0.0;
+            const double dll = (both && !same) ? dl : 0.0;
+            const double ap = (sbar * bq[p] - u[p]) * bqq;
+            acc_s = fma(ap, ds, acc_s);
+            acc_l = fma(ap, dll, acc_l);
+        });
+    });
+    acc_s = group_sum<P>(acc_s);
+    acc_l = group_sum<P>(acc_l);
+    if (r == 0) acc_s = fma(sbar, 2.0 * a.sigma_amp, acc_s);   // dK_ii / dsigma
+    if (!live || r != 0) acc_s = acc_l = 0.0;
+    __shared__ double sh[2 * (kBlock / 64)];
+    block_sum2(acc_s, acc_l, sh);
+    if (tid == 0) {
+        a.theta_part[2 * blockIdx.x] = acc_s;
+        a.theta_part[2 * blockIdx.x + 1] = acc_l;
+    }
+}
+
+// ---- dense block: xibar0 = L0^T w0 and the Cholesky adjoint contribution
+template <typename TS, int KIND>
+__global__ __launch_bounds__(VECCHIA_N0MAX) void adj_dense_kernel(AdjArgs<TS> a) {
+    constexpr int LD = VECCHIA_N0MAX + 1;
+    __shared__ double X[VECCHIA_N0MAX * LD];
+    __shared__ double G[VECCHIA_N0MAX], Z[VECCHIA_N0MAX], H[VECCHIA_N0MAX];
+    __shared__ double sh[2 * (VECCHIA_N0MAX / 64)];
+    const int i = threadIdx.x;
+    const int n0 = a.n0;
+    const double* L = a.l0;
+    if (i < n0) {
+        double g = a.vbar ? (double)a.w[i] : 0.0;
+        if (a.xibar_in) g -= a.t0[i];
+        G[i] = g;
+        Z[i] = (double)a.xi[i];
+    }
+    __syncthreads();
+    if (i < n0) {
+        double h = 0.0, xb = 0.0;
+        for (int m = i; m < n0; ++m) {
+            h = fma(L[m * n0 + i], G[m], h);
+            if (a.vbar) xb = fma(L[m * n0 + i], (double)a.w[m], xb);
+        }
+        H[i] = h;
+        if (a.vbar) a.xibar[i] = (TS)xb;
+    }
+    __syncthreads();
+    // X = M L0^-1, row i: x L0 = m  (backward over columns)
+    if (i < n0) {
+        for (int j = n0 - 1; j >= 0; --j) {
+            double m = j < i ? H[i] * Z[j] : (j == i ? 0.5 * H[i] * Z[i] + a.ldbar : 0.0);
+            for (int l = j + 1; l < n0; ++l) m = fma(-X[i * LD + l], L[l * n0 + j], m);
+            X[i * LD + j] = m / L[j * n0 + j];
+        }
+    }
+    __syncthreads();
+    // Y = L0^-T X, column i: L0^T y = x  (backward over rows), in place
+    if (i < n0) {
+        for (int rr = n0 - 1; rr >= 0; --rr) {
+            double m = X[rr * LD + i];
+            for (int l = rr + 1; l < n0; ++l) m = fma(-L[l * n0 + rr], X[l * LD + i], m);
+            X[rr * LD + i] = m / L[rr * n0 + rr];
+        }
+    }
+    __syncthreads();
+    double acc_s = 0.0, acc_l = 0.0;
+    if (i < n0) {
+        const double p0 = (double)a.x[i * 3], p1 = (double)a.x[i * 3 + 1], p2 = (double)a.x[i * 3 + 2];
+        for (int j = 0; j < n0; ++j) {
+            double kap, dl;
+            cov_and_dell<KIND>(sqdist3(p0, p1, p2, (double)a.x[j * 3], (double)a.x[j * 3 + 1], (double)a.x[j * 3 + 2]),
+                               a.cov, kap, dl);
+            const double y = X[i * LD + j];
+            acc_s = fma(y, i == j ? 2.0 * a.sigma_amp : 2.0 * kap / a.sigma_amp, acc_s);
+            acc_l = fma(y, i == j ? 0.0 : dl, acc_l);
+        }
+    }
+    block_sum2(acc_s, acc_l, sh);
+    if (i == 0) {
+        a.theta_dense[0] = acc_s;
+        a.theta_dense[1] = acc_l;
+    }
+}
+
+// ---- theta = sum of the per-block partials (compensated, fixed order) + dense
+__global__ __launch_bounds__(1024) void adj_theta_reduce_kernel(const double* __restrict__ part, int64_t nblocks,
+                                                                const double* __restrict__ dense,
+                                                                double* __restrict__ out) {
+    __shared__ double S[2][1024], C[2][1024];
+    double s[2] = {0.0, 0.0}, c[2] = {0.0, 0.0};
+    for (int64_t b = threadIdx.x; b < nblocks; b += 1024)
+        for (int t = 0; t < 2; ++t) {
+            const double x = part[2 * b + t];
+            const double y = s[t] + x;
+            c[t] += fabs(s[t]) >= fabs(x) ? (s[t] - y) + x : (x - y) + s[t];
+            s[t] = y;
+        }
+    for (int t = 0; t < 2; ++t) {
+        S[t][threadIdx.x] = s[t];
+        C[t][threadIdx.x] = c[t];
+    }
+    __syncthreads();
+    for (int stride = 512; stride > 0; stride >>= 1) {
+        if ((int)threadIdx.x < stride)
+            for (int t = 0; t < 2; ++t) {
+                const double x = S[t][threadIdx.x + stride];
+                const double y = S[t][threadIdx.x] + x;
+                const double e = fabs(S[t][threadIdx.x]) >= fabs(x) ? (S[t][threadIdx.x] - y) + x
+                                                                    : (x - y) + S[t][threadIdx.x];
+                S[t][threadIdx.x] = y;
+                C[t][threadIdx.x] += C[t][threadIdx.x + stride] + e;
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int t = 0; t < 2; ++t) out[t] = (S[t][0] + C[t][0]) + dense[t];
+}
+
+template <typename TS, int KP, int KIND>
+static hipError_t backward_t(const BackwardLaunch& p, hipStream_t s) {
+    AdjArgs<TS> a;
+    a.x = static_cast<const TS*>(p.x);
+    a.nbr = p.nbr;
+    a.child_ptr = p.child_ptr;
+    a.child = p.child;
+    a.b = static_cast<const TS*>(p.b);
+    a.sigma = static_cast<const TS*>(p.sigma);
+    a.l0 = p.l0;
+    a.xi = static_cast<const TS*>(p.xi);
+    a.v = static_cast<const TS*>(p.v);
+    a.vbar = static_cast<const TS*>(p.vbar);
+    a.xibar_in = static_cast<const TS*>(p.xibar_in);
+    a.w = static_cast<TS*>(p.w);
+    a.xibar = static_cast<TS*>(p.xibar);
+    a.vbar_out = static_cast<TS*>(p.vbar_out);
+    a.t0 = p.t0;
+    a.theta_part = p.theta_part;
+    a.theta_dense = p.theta_dense;
+    a.theta_out = p.theta_out;
+    a.n = p.n;
+    a.ns = p.ns;
+    a.n0 = p.n0;
+    a.kp = KP;
+    a.ldbar = p.ldbar;
+    a.sigma_amp = p.kern.sigma;
+    a.diag = p.kern.sigma * p.kern.sigma + p.kern.nugget;
+    a.cov = make_cov<double>(p.kern);
+    constexpr int P = factor_lanes(VECCHIA_FP64, KP);
+    a.nblocks = (p.ns + kBlock / P - 1) / (kBlock / P);
+    hipError_t e = hipSuccess;
+    if (p.vbar) {
+        for (int l = p.n_levels; l >= 0; --l) {
+            const int64_t j0 = l == 0 ? 0 : p.level_ptr[l], j1 = l == 0 ? p.n0 : p.level_ptr[l + 1];
+            if (j1 <= j0) continue;
+            hipLaunchKernelGGL((adj_sweep_kernel<TS, KP>), dim3((unsigned)((j1 - j0 + kBlock - 1) / kBlock)),
+                               dim3(kBlock), 0, s, a, j0, j1);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+    }
+    if (p.xibar_in) {
+        hipLaunchKernelGGL((adj_inverse_kernel<TS, KP>), dim3((unsigned)((p.n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                           s, a);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL((adj_dense_inverse_kernel<TS>), dim3(1), dim3(VECCHIA_N0MAX), 0, s, a);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (a.nblocks > 0) {
+        hipLaunchKernelGGL((adj_theta_kernel<TS, KP, KIND>), dim3((unsigned)a.nblocks), dim3(kBlock), 0, s, a);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((adj_dense_kernel<TS, KIND>), dim3(1), dim3(VECCHIA_N0MAX), 0, s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(adj_theta_reduce_kernel, dim3(1), dim3(1024), 0, s, a.theta_part, a.nblocks, a.theta_dense,
+                       a.theta_out);
+    return hipGetLastError();
+}
+
+template <typename TS, int KP>
+static hipError_t backward_kind(const BackwardLaunch& p, hipStream_t s) {
+    switch (p.kern.kind) {
+        case 0: return backward_t<TS, KP, 0>(p, s);
+        case 1: return backward_t<TS, KP, 1>(p, s);
+        case 2: return backward_t<TS, KP, 2>(p, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename TS>
+static hipError_t backward_width(const BackwardLaunch& p, hipStream_t s) {
+    switch (p.kp) {
+        case 8: return backward_kind<TS, 8>(p, s);
+        case 16: return backward_kind<TS, 16>(p, s);
+        case 32: return backward_kind<TS, 32>(p, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_backward(const BackwardLaunch& p, hipStream_t s) {
+    return p.precision == VECCHIA_FP32 ? backward_width<float>(p, s) : backward_width<double>(p, s);
+}
+
+}  // namespace vk

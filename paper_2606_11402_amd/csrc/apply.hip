@@ -8,10 +8,12 @@
 //
 // Both are HBM bound gather-dots: one lane per point, 64 points per wave
 // reading entry m of their tiled rows as one contiguous 256-byte segment
-// (neighbour index and coefficient), then gathering v.  FP32 storage uses
-// FP32 accumulation.
+// (neighbour index and coefficient), then gathering v.  The forward
+// accumulates in the storage precision, the inverse in double.
 #include "common.h"
 #include "lanes.h"
+
+#include <type_traits>
 
 namespace vk {
 
@@ -25,18 +27,24 @@ __global__ __launch_bounds__(kBlock) void apply_kernel(const int32_t* __restrict
     const int64_t sp = first_tile * kTile + blk * kBlock + threadIdx.x;
     if (sp < s_begin || sp >= s_end) return;
     const int64_t base = (sp >> 6) * (int64_t)KP * kTile + (sp & 63);
+    // The inverse subtracts two nearly equal numbers (v_i and its conditional
+    // mean) and divides by a possibly small sigma_i, so it accumulates in
+    // double; double FMA runs at the FP32 rate on CDNA4 and this kernel is
+    // bound by HBM, so the wider accumulator is free.  The forward sum has no
+    // cancellation and accumulates in the storage precision.
+    using Acc = typename std::conditional<INVERSE, double, T>::type;
     const T* vsrc = INVERSE ? in : out;
-    T acc = T(0);
+    Acc acc = Acc(0);
 #pragma unroll
     for (int m = 0; m < KP; ++m) {
         const int32_t j = __builtin_nontemporal_load(nbr + base + m * kTile);
         const T w = __builtin_nontemporal_load(b + base + m * kTile);
         const T vj = vsrc[j >= 0 ? j : 0];
-        acc = fma(w, j >= 0 ? vj : T(0), acc);
+        acc = fma((Acc)w, (Acc)(j >= 0 ? vj : T(0)), acc);
     }
     const int64_t s = n0 + sp;
     if constexpr (INVERSE) {
-        out[s] = (in[s] - acc) / sig[sp];
+        out[s] = (T)(((Acc)in[s] - acc) / (Acc)sig[sp]);
     } else {
         out[s] = fma(sig[sp], in[s], acc);
     }
@@ -100,12 +108,10 @@ struct Neumaier {
 };
 
 constexpr int kLdThreads = 1024;
+constexpr int kLdBlocks = 256;   // first stage: one workgroup per CU
 
-__global__ __launch_bounds__(kLdThreads) void logdet_kernel(const double* __restrict__ part, int64_t n,
-                                                            const double* __restrict__ ld0, double* __restrict__ out) {
-    __shared__ double S[kLdThreads], C[kLdThreads];
-    Neumaier acc;
-    for (int64_t i = threadIdx.x; i < n; i += kLdThreads) acc.add(part[i]);
+// Compensated sum of S[0..kLdThreads) (pairs s, c) inside one workgroup.
+__device__ Neumaier block_reduce(Neumaier acc, double* S, double* C) {
     S[threadIdx.x] = acc.s;
     C[threadIdx.x] = acc.c;
     __syncthreads();
@@ -118,23 +124,65 @@ __global__ __launch_bounds__(kLdThreads) void logdet_kernel(const double* __rest
         }
         __syncthreads();
     }
+    return Neumaier{S[0], C[0]};
+}
+
+// Stage 1: workgroup g sums a contiguous slice of the per-block partials
+// (fixed slices, fixed order: the result does not depend on scheduling).
+__global__ __launch_bounds__(kLdThreads) void logdet_partial_kernel(const double* __restrict__ part, int64_t n,
+                                                                    double* __restrict__ stage) {
+    __shared__ double S[kLdThreads], C[kLdThreads];
+    const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = (int64_t)blockIdx.x * per, hi = lo + per < n ? lo + per : n;
+    Neumaier acc;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kLdThreads) acc.add(part[i]);
+    const Neumaier tot = block_reduce(acc, S, C);
     if (threadIdx.x == 0) {
-        Neumaier a{S[0], C[0]};
+        stage[2 * blockIdx.x] = tot.s;
+        stage[2 * blockIdx.x + 1] = tot.c;
+    }
+}
+
+// Stage 2: the stage-1 pairs, the dense block and the recomputed points.
+__global__ __launch_bounds__(kLdThreads) void logdet_final_kernel(const double* __restrict__ stage, int nstage,
+                                                                  const double* __restrict__ ld0,
+                                                                  const uint64_t* __restrict__ status,
+                                                                  double* __restrict__ out) {
+    __shared__ double S[kLdThreads], C[kLdThreads];
+    Neumaier acc;
+    for (int i = threadIdx.x; i < nstage; i += kLdThreads) acc.merge(Neumaier{stage[2 * i], stage[2 * i + 1]});
+    Neumaier a = block_reduce(acc, S, C);
+    if (threadIdx.x == 0) {
         a.add(*ld0);
+        a.add((double)(long long)status[3] / 4294967296.0);   // recomputed points, fixed point 2^-32
         out[0] = 2.0 * (a.s + a.c);
     }
 }
 
-hipError_t launch_logdet(const double* ldpart, int64_t nparts, const double* ld0, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(logdet_kernel, dim3(1), dim3(kLdThreads), 0, s, ldpart, nparts, ld0, out);
+hipError_t launch_logdet(const double* ldpart, int64_t nparts, const double* ld0, const uint64_t* status,
+                         double* stage, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(logdet_partial_kernel, dim3(kLdBlocks), dim3(kLdThreads), 0, s, ldpart, nparts, stage);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(logdet_final_kernel, dim3(1), dim3(kLdThreads), 0, s, stage, kLdBlocks, ld0, status, out);
     return hipGetLastError();
 }
 
-hipError_t launch_factor_sparse_f32(const FactorLaunch& a, hipStream_t s);
-hipError_t launch_factor_sparse_f64(const FactorLaunch& a, hipStream_t s);
+hipError_t launch_factor_sparse_f32_k8(const FactorLaunch& a, hipStream_t s);
+hipError_t launch_factor_sparse_f32_k16(const FactorLaunch& a, hipStream_t s);
+hipError_t launch_factor_sparse_f32_k32(const FactorLaunch& a, hipStream_t s);
+hipError_t launch_factor_sparse_f64_k8(const FactorLaunch& a, hipStream_t s);
+hipError_t launch_factor_sparse_f64_k16(const FactorLaunch& a, hipStream_t s);
+hipError_t launch_factor_sparse_f64_k32(const FactorLaunch& a, hipStream_t s);
 
 hipError_t launch_factor_sparse(const FactorLaunch& a, hipStream_t s) {
-    return a.precision == VECCHIA_FP32 ? launch_factor_sparse_f32(a, s) : launch_factor_sparse_f64(a, s);
+    const bool f32 = a.precision == VECCHIA_FP32;
+    switch (a.kp) {
+        case 8: return f32 ? launch_factor_sparse_f32_k8(a, s) : launch_factor_sparse_f64_k8(a, s);
+        case 16: return f32 ? launch_factor_sparse_f32_k16(a, s) : launch_factor_sparse_f64_k16(a, s);
+        case 32: return f32 ? launch_factor_sparse_f32_k32(a, s) : launch_factor_sparse_f64_k32(a, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace vk

@@ -11,6 +11,10 @@
 
 using namespace vk;
 
+// FP32 path: a point is recomputed in double when one of its pivots falls
+// below 2^-kDefaultRedoLog2 * K_ii (view->redo_log2 == 0).
+constexpr int kDefaultRedoLog2 = 16;
+
 namespace {
 
 // ---- per-kernel timing with HIP events on the launch stream ---------------
@@ -148,6 +152,11 @@ extern "C" int vecchia_factor(vecchia_view* view, const vecchia_kernel* kern, vo
     a.sigma = ws<char>(view, lay.sigma);
     a.ldpart = ws<double>(view, lay.ldpart);
     a.status = ws<uint64_t>(view, lay.status);
+    a.redo = ws<uint32_t>(view, lay.redo);
+    {
+        const int bits = view->redo_log2 == 0 ? kDefaultRedoLog2 : view->redo_log2;
+        a.redo_ratio = bits < 0 ? 0.0 : std::ldexp(1.0, -bits);
+    }
     a.kern = *kern;
     if (lay.ns > 0) {
         e = timed("factor_sparse", s, [&] { return launch_factor_sparse(a, s); });
@@ -208,7 +217,8 @@ extern "C" int vecchia_logdet(const vecchia_view* view, double* out, void* strea
     if (!out) return vecchia_set_error(VECCHIA_EINVAL, "vecchia_logdet: out is NULL");
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = timed("logdet", s, [&] {
-        return launch_logdet(ws<double>(view, lay.ldpart), lay.ns > 0 ? lay.nparts : 0, ws<double>(view, lay.ld0), out, s);
+        return launch_logdet(ws<double>(view, lay.ldpart), lay.ns > 0 ? lay.nparts : 0, ws<double>(view, lay.ld0),
+                             ws<uint64_t>(view, lay.status), ws<double>(view, lay.ldstage), out, s);
     });
     if (e != hipSuccess) return hip_fail(e, "vecchia_logdet");
     return VECCHIA_OK;
@@ -229,6 +239,20 @@ extern "C" int vecchia_status(const vecchia_view* view, void* stream, int64_t* f
     if (st[0] != kStatusNone)
         return vecchia_set_error(VECCHIA_ENOTPD, "covariance not positive definite at storage position %llu (%llu points)",
                                  (unsigned long long)st[0], (unsigned long long)st[1]);
+    return VECCHIA_OK;
+}
+
+extern "C" int vecchia_factor_counts(const vecchia_view* view, void* stream, int64_t* not_pd, int64_t* recomputed) {
+    vecchia_clear_error();
+    Layout lay;
+    int rc = check_view(view, &lay, "vecchia_factor_counts");
+    if (rc) return rc;
+    uint64_t st[4] = {0, 0, 0, 0};
+    hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    if (e == hipSuccess) e = hipMemcpy(st, ws<uint64_t>(view, lay.status), sizeof(st), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "vecchia_factor_counts");
+    if (not_pd) *not_pd = (int64_t)st[1];
+    if (recomputed) *recomputed = (int64_t)st[2];
     return VECCHIA_OK;
 }
 
@@ -297,16 +321,69 @@ extern "C" int vecchia_profile_reset(void) {
 }
 
 extern "C" int vecchia_backward_scratch_bytes(const vecchia_view* view, size_t* bytes) {
-    (void)view;
-    (void)bytes;
-    return vecchia_set_error(VECCHIA_EUNSUPPORTED, "vecchia_backward_scratch_bytes: adjoint not built yet");
+    vecchia_clear_error();
+    Layout lay;
+    int rc = check_view(view, &lay, "vecchia_backward_scratch_bytes");
+    if (rc) return rc;
+    if (!bytes) return vecchia_set_error(VECCHIA_EINVAL, "vecchia_backward_scratch_bytes: bytes is NULL");
+    *bytes = backward_scratch(view->n, view->kp, view->n0, view->precision).total;
+    return VECCHIA_OK;
 }
 
 extern "C" int vecchia_backward(const vecchia_view* view, const vecchia_kernel* kern, const void* xi, const void* v,
                                 const void* v_bar, const void* xi_bar_in, double logdet_bar, void* xi_bar,
                                 void* v_bar_out, double* theta_bar, void* scratch, size_t scratch_bytes,
                                 void* stream) {
-    (void)view, (void)kern, (void)xi, (void)v, (void)v_bar, (void)xi_bar_in, (void)logdet_bar, (void)xi_bar;
-    (void)v_bar_out, (void)theta_bar, (void)scratch, (void)scratch_bytes, (void)stream;
-    return vecchia_set_error(VECCHIA_EUNSUPPORTED, "vecchia_backward: adjoint not built yet");
+    vecchia_clear_error();
+    Layout lay;
+    int rc = check_view(view, &lay, "vecchia_backward");
+    if (rc) return rc;
+    if ((rc = check_kernel(kern))) return rc;
+    if (!view->child_ptr || !view->child)
+        return vecchia_set_error(VECCHIA_EINVAL, "vecchia_backward: the view needs child_ptr and child");
+    if (!xi || !v || !theta_bar || !scratch)
+        return vecchia_set_error(VECCHIA_EINVAL, "vecchia_backward: xi, v, theta_bar and scratch must be set");
+    if (v_bar && !xi_bar) return vecchia_set_error(VECCHIA_EINVAL, "vecchia_backward: v_bar given without xi_bar");
+    if (xi_bar_in && !v_bar_out)
+        return vecchia_set_error(VECCHIA_EINVAL, "vecchia_backward: xi_bar_in given without v_bar_out");
+    if (!std::isfinite(logdet_bar)) return vecchia_set_error(VECCHIA_EINVAL, "vecchia_backward: logdet_bar not finite");
+    const BackwardScratch sc = backward_scratch(view->n, view->kp, view->n0, view->precision);
+    if (scratch_bytes < sc.total)
+        return vecchia_set_error(VECCHIA_ENOMEM, "vecchia_backward: scratch has %zu bytes, needs %zu", scratch_bytes,
+                                 sc.total);
+    if (reinterpret_cast<uintptr_t>(scratch) & 255)
+        return vecchia_set_error(VECCHIA_EINVAL, "vecchia_backward: scratch must be 256-byte aligned");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* sb = static_cast<char*>(scratch);
+    BackwardLaunch p;
+    p.precision = view->precision;
+    p.kp = view->kp;
+    p.n0 = view->n0;
+    p.n_levels = view->n_levels;
+    p.n = view->n;
+    p.ns = lay.ns;
+    p.level_ptr = view->level_ptr;
+    p.x = view->x;
+    p.xi = xi;
+    p.v = v;
+    p.vbar = v_bar;
+    p.xibar_in = xi_bar_in;
+    p.b = ws<char>(view, lay.b);
+    p.sigma = ws<char>(view, lay.sigma);
+    p.nbr = view->nbr;
+    p.child_ptr = view->child_ptr;
+    p.child = view->child;
+    p.l0 = ws<double>(view, lay.l0);
+    p.w = sb + sc.w;
+    p.xibar = xi_bar;
+    p.vbar_out = v_bar_out;
+    p.t0 = reinterpret_cast<double*>(sb + sc.t0);
+    p.theta_part = reinterpret_cast<double*>(sb + sc.part);
+    p.theta_dense = reinterpret_cast<double*>(sb + sc.dense);
+    p.theta_out = theta_bar;
+    p.ldbar = logdet_bar;
+    p.kern = *kern;
+    hipError_t e = timed("backward", s, [&] { return launch_backward(p, s); });
+    if (e != hipSuccess) return hip_fail(e, "vecchia_backward");
+    return VECCHIA_OK;
 }

@@ -26,7 +26,7 @@ __host__ __device__ constexpr int factor_lanes(int precision, int kp) {
 struct Layout {
     int64_t ns = 0, ntiles = 0, nparts = 0;
     size_t esz = 0;
-    size_t b = 0, sigma = 0, l0 = 0, ldpart = 0, ld0 = 0, status = 0, total = 0;
+    size_t b = 0, sigma = 0, l0 = 0, ldpart = 0, ld0 = 0, ldstage = 0, status = 0, redo = 0, total = 0;
 };
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -49,8 +49,12 @@ inline Layout workspace_layout(int64_t n, int kp, int n0, int precision) {
     off = align256(off + (size_t)(w.nparts > 0 ? w.nparts : 1) * sizeof(double));
     w.ld0 = off;
     off = align256(off + sizeof(double));
+    w.ldstage = off;
+    off = align256(off + 2 * 256 * sizeof(double));
     w.status = off;
-    off = align256(off + 2 * sizeof(uint64_t));
+    off = align256(off + 4 * sizeof(uint64_t));
+    w.redo = off;
+    if (precision == VECCHIA_FP32) off = align256(off + (size_t)(w.ns > 0 ? w.ns : 1) * sizeof(uint32_t));
     w.total = off;
     return w;
 }
@@ -120,6 +124,8 @@ struct FactorLaunch {
     void* sigma;
     double* ldpart;
     uint64_t* status;
+    uint32_t* redo;
+    double redo_ratio;
     vecchia_kernel kern;
 };
 hipError_t launch_factor_sparse(const FactorLaunch& a, hipStream_t stream);
@@ -131,5 +137,47 @@ hipError_t launch_forward_level(int precision, int kp, const int32_t* nbr, const
 hipError_t launch_inverse_dense(int precision, const double* l0, int n0, const void* v, void* xi, hipStream_t stream);
 hipError_t launch_inverse_sparse(int precision, int kp, const int32_t* nbr, const void* b, const void* sigma,
                                  const void* v, void* xi, int n0, int64_t ns, hipStream_t stream);
-hipError_t launch_logdet(const double* ldpart, int64_t nparts, const double* ld0, double* out, hipStream_t stream);
+struct BackwardLaunch {
+    int precision, kp, n0, n_levels;
+    int64_t n, ns;
+    const int32_t* level_ptr;   // host
+    const void *x, *xi, *v, *vbar, *xibar_in, *b, *sigma;
+    const int32_t* nbr;
+    const int64_t* child_ptr;
+    const int32_t* child;
+    const double* l0;
+    void *w, *xibar, *vbar_out;
+    double *t0, *theta_part, *theta_dense, *theta_out;
+    double ldbar;
+    vecchia_kernel kern;
+};
+hipError_t launch_backward(const BackwardLaunch& p, hipStream_t stream);
+
+// Scratch of vecchia_backward: w (N values), t0 (n0 doubles), theta partials
+// (2 doubles per block of the theta kernel), dense theta (2 doubles).
+struct BackwardScratch {
+    size_t w = 0, t0 = 0, part = 0, dense = 0, total = 0;
+    int64_t nblocks = 0;
+};
+inline BackwardScratch backward_scratch(int64_t n, int kp, int n0, int precision) {
+    BackwardScratch b;
+    const int64_t ns = n - n0;
+    const int pts = kBlock / factor_lanes(VECCHIA_FP64, kp);
+    b.nblocks = (ns + pts - 1) / pts;
+    size_t off = 0;
+    b.w = off;
+    off = align256(off + (size_t)n * (precision == VECCHIA_FP64 ? 8 : 4));
+    b.t0 = off;
+    off = align256(off + (size_t)n0 * sizeof(double));
+    b.part = off;
+    off = align256(off + (size_t)(b.nblocks > 0 ? b.nblocks : 1) * 2 * sizeof(double));
+    b.dense = off;
+    off = align256(off + 2 * sizeof(double));
+    b.total = off;
+    return b;
+}
+
+constexpr int kLogdetStage = 256;   // first-stage workgroups of the logdet reduction
+hipError_t launch_logdet(const double* ldpart, int64_t nparts, const double* ld0, const uint64_t* status,
+                         double* stage, double* out, hipStream_t stream);
 }  // namespace vk

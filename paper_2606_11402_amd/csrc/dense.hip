@@ -19,8 +19,10 @@ __global__ __launch_bounds__(kDenseThreads) void factor_dense_kernel(const TX* _
     __shared__ double A[VECCHIA_N0MAX * kLd];
     const int i = threadIdx.x;
     if (i == 0) {
-        status[0] = kStatusNone;
-        status[1] = 0;
+        status[0] = kStatusNone;   // first failing storage position
+        status[1] = 0;             // failing points
+        status[2] = 0;             // FP32 path: points recomputed in double
+        status[3] = 0;             // their sum of log sigma, fixed point
     }
     if (i < n0) {
         const double a0 = (double)x[i * 3 + 0], a1 = (double)x[i * 3 + 1], a2 = (double)x[i * 3 + 2];

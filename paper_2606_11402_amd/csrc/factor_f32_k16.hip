@@ -1,0 +1,15 @@
+// Instantiations of the sparse factor kernels: float storage, k padded to 16.
+#include "factor_kernel.h"
+
+namespace vk {
+
+hipError_t launch_factor_sparse_f32_k16(const FactorLaunch& a, hipStream_t s) {
+    switch (a.kind) {
+        case 0: return launch_factor_sparse_t<float, 16, 0>(a, s);
+        case 1: return launch_factor_sparse_t<float, 16, 1>(a, s);
+        case 2: return launch_factor_sparse_t<float, 16, 2>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace vk

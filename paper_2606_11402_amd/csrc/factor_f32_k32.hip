@@ -1,0 +1,15 @@
+// Instantiations of the sparse factor kernels: float storage, k padded to 32.
+#include "factor_kernel.h"
+
+namespace vk {
+
+hipError_t launch_factor_sparse_f32_k32(const FactorLaunch& a, hipStream_t s) {
+    switch (a.kind) {
+        case 0: return launch_factor_sparse_t<float, 32, 0>(a, s);
+        case 1: return launch_factor_sparse_t<float, 32, 1>(a, s);
+        case 2: return launch_factor_sparse_t<float, 32, 2>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace vk

@@ -30,6 +30,8 @@
 // position in status[0] (status[1] counts failing points).
 #pragma once
 
+#include <algorithm>
+
 #include "common.h"
 #include "lanes.h"
 
@@ -42,13 +44,19 @@ struct FactorArgs {
     T* b;                  // tiled coefficients
     T* sigma;              // conditional standard deviation per sparse index
     double* ldpart;        // per-block sum of log sigma
-    uint64_t* status;
+    uint64_t* status;      // [first bad position, bad count, redo count, redo log-sigma sum (fixed point)]
+    uint32_t* redo;        // FP32 path: sparse indices recomputed in double
     int64_t ns;
     int64_t nblocks;
     int n0;
     Cov<T> cov;
     double diag;           // K_ii = sigma^2 + nugget, double
+    double redo_ratio;     // FP32 path: recompute a point in double when a pivot < redo_ratio * K_ii
 };
+
+// Fixed-point scale of the log-sigma sum of recomputed points: integer
+// additions commute, so the sum does not depend on the order of the atomics.
+constexpr double kFixScale = 4294967296.0;  // 2^32
 
 template <int P>
 __host__ __device__ constexpr int row_off(int p) {
@@ -93,38 +101,28 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
     return v;
 }
 
-template <typename T, int K, int P, int KIND, bool REFINE>
-__global__ __launch_bounds__(kBlock) void factor_sparse_kernel(FactorArgs<T> a) {
-    static_assert(K % P == 0, "K must be a multiple of P");
+// Coordinates of the neighbours of the rows this lane owns (-1 padded rows
+// read point 0 and are masked by ok).
+template <typename T, typename TX, int K, int P>
+__device__ __forceinline__ void gather_rows(const TX* __restrict__ x, const int32_t* __restrict__ nbr, int64_t base,
+                                            int r, T* c0, T* c1, T* c2, int* ok) {
     constexpr int R = K / P;
-    constexpr int NA = P * R * (R + 1) / 2;
-    constexpr int PTS = kBlock / P;
-
-    const int tid = threadIdx.x;
-    const int r = tid % P;
-    const int64_t blk = xcd_block(blockIdx.x, a.nblocks);
-    const int64_t sp_raw = blk * PTS + tid / P;
-    const bool live = sp_raw < a.ns;
-    const int64_t sp = live ? sp_raw : a.ns - 1;      // dead lanes mirror a live point
-    const int64_t base = (sp >> 6) * (int64_t)K * kTile + (sp & 63);
-
-    // ---- gather: the point, and the neighbours of the rows this lane owns
-    const T* xt = a.x + (int64_t)(a.n0 + sp) * 3;
-    const T t0 = xt[0], t1 = xt[1], t2 = xt[2];
-    T c0[R], c1[R], c2[R];
-    int ok[R];
     static_for<0, R>([&](auto PI) {
         constexpr int p = PI;
-        const int32_t j = a.nbr[base + (int64_t)(p * P + r) * kTile];
+        const int32_t j = nbr[base + (int64_t)(p * P + r) * kTile];
         ok[p] = j >= 0;
         const int64_t jj = j >= 0 ? j : 0;
-        c0[p] = a.x[jj * 3 + 0];
-        c1[p] = a.x[jj * 3 + 1];
-        c2[p] = a.x[jj * 3 + 2];
+        c0[p] = (T)x[jj * 3 + 0];
+        c1[p] = (T)x[jj * 3 + 1];
+        c2[p] = (T)x[jj * 3 + 2];
     });
+}
 
-    // ---- assemble the strictly lower part of K_cc, k_ci and the diagonal
-    T A[NA];
+// Strictly lower part of K_cc into A (diagonal slots and padded rows zero).
+template <typename T, int K, int P, int KIND>
+__device__ __forceinline__ void assemble_kcc(const T* c0, const T* c1, const T* c2, const int* ok, int r,
+                                             const Cov<T>& cov, T* A) {
+    constexpr int R = K / P;
     static_for<0, K>([&](auto LI) {
         constexpr int l = LI, pl = l / P, rl = l % P;
         const T y0 = group_bcast<P, rl>(c0[pl]);
@@ -133,28 +131,25 @@ __global__ __launch_bounds__(kBlock) void factor_sparse_kernel(FactorArgs<T> a) 
         const int okl = group_bcast<P, rl>(ok[pl]);
         static_for<pl, R>([&](auto PI) {
             constexpr int p = PI;
-            const T val = cov_r2<KIND>(sqdist3(c0[p], c1[p], c2[p], y0, y1, y2), a.cov);
+            const T val = cov_r2<KIND>(sqdist3(c0[p], c1[p], c2[p], y0, y1, y2), cov);
             const bool keep = (ok[p] & okl & (int)(l < p * P + r)) != 0;
             A[row_off<P>(p) + l] = keep ? val : T(0);
         });
     });
-    T kc[R];
-    double Dg[R];
-    static_for<0, R>([&](auto PI) {
-        constexpr int p = PI;
-        const T val = cov_r2<KIND>(sqdist3(c0[p], c1[p], c2[p], t0, t1, t2), a.cov);
-        kc[p] = ok[p] ? val : T(0);
-        Dg[p] = ok[p] ? a.diag : 1.0;
-    });
+}
 
-    // ---- right-looking Cholesky of K_cc with double pivots
-    T Inv[R];
-    bool bad = false;
+// Right-looking Cholesky of K_cc in place: A receives the strictly lower
+// part of L (zero elsewhere), Inv[p] = 1/L_ii of the lane's rows.  Pivots
+// d_j = K_jj - sum_m L_jm^2 live in Dg (double) for both storage types.
+template <typename T, int K, int P>
+__device__ __forceinline__ void cholesky_kcc(T* A, double* Dg, T* Inv, int r, bool& bad, double& minpiv) {
+    constexpr int R = K / P;
     static_for<0, R>([&](auto PI) { Inv[(int)PI] = T(0); });
     static_for<0, K>([&](auto JI) {
         constexpr int j = JI, pj = j / P, rj = j % P;
         const double d = group_bcast<P, rj>(Dg[pj]);
         bad |= !(d > 0.0);
+        minpiv = fmin(minpiv, d);
         const T invt = (T)rsqrt_f64(d);
         Inv[pj] = (r == rj) ? invt : Inv[pj];
         static_for<pj, R>([&](auto PI) {
@@ -178,9 +173,43 @@ __global__ __launch_bounds__(kBlock) void factor_sparse_kernel(FactorArgs<T> a) 
             });
         });
     });
+}
+
+// Eq. (2) for the sparse point sp, computed in type T from coordinates of
+// type TX.  On return the lane holds b for its rows in bv[], the group holds
+// sigma^2 (double), the smallest pivot and whether a pivot or the variance
+// was not positive.
+template <typename T, typename TX, int K, int P, int KIND, bool REFINE>
+__device__ __forceinline__ void factor_point(const TX* __restrict__ x, const int32_t* __restrict__ nbr, int n0,
+                                             int64_t sp, int r, const Cov<T>& cov, double diag, T* bv,
+                                             double& s2_out, double& minpiv_out, bool& bad_out) {
+    constexpr int R = K / P;
+    constexpr int NA = P * R * (R + 1) / 2;
+    const int64_t base = (sp >> 6) * (int64_t)K * kTile + (sp & 63);
+
+    const TX* xt = x + (int64_t)(n0 + sp) * 3;
+    const T t0 = (T)xt[0], t1 = (T)xt[1], t2 = (T)xt[2];
+    T c0[R], c1[R], c2[R];
+    int ok[R];
+    gather_rows<T, TX, K, P>(x, nbr, base, r, c0, c1, c2, ok);
+
+    T A[NA];
+    assemble_kcc<T, K, P, KIND>(c0, c1, c2, ok, r, cov, A);
+    T kc[R];
+    double Dg[R];
+    static_for<0, R>([&](auto PI) {
+        constexpr int p = PI;
+        const T val = cov_r2<KIND>(sqdist3(c0[p], c1[p], c2[p], t0, t1, t2), cov);
+        kc[p] = ok[p] ? val : T(0);
+        Dg[p] = ok[p] ? diag : 1.0;
+    });
+
+    T Inv[R];
+    bool bad = false;
+    double minpiv = diag;
+    cholesky_kcc<T, K, P>(A, Dg, Inv, r, bad, minpiv);
 
     // ---- y = L^-1 k_ci, sigma^2 = K_ii - y.y (double), b = L^-T y
-    T bv[R];
     static_for<0, R>([&](auto PI) { bv[(int)PI] = kc[(int)PI]; });
     double yy = 0.0;
     static_for<0, K>([&](auto JI) {
@@ -193,7 +222,7 @@ __global__ __launch_bounds__(kBlock) void factor_sparse_kernel(FactorArgs<T> a) 
             bv[p] = fma(-A[row_off<P>(p) + j], yj, bv[p]);
         });
     });
-    double s2 = a.diag - yy;
+    double s2 = diag - yy;
     upper_solve<T, K, P>(A, Inv, bv, r);
 
     if constexpr (REFINE) {
@@ -206,7 +235,7 @@ __global__ __launch_bounds__(kBlock) void factor_sparse_kernel(FactorArgs<T> a) 
         double res[R];
         static_for<0, R>([&](auto PI) {
             constexpr int p = PI;
-            res[p] = (double)kc[p] - (ok[p] ? a.diag : 1.0) * (double)bv[p];
+            res[p] = (double)kc[p] - (ok[p] ? diag : 1.0) * (double)bv[p];
         });
         static_for<0, K>([&](auto LI) {
             constexpr int l = LI, pl = l / P, rl = l % P;
@@ -217,7 +246,7 @@ __global__ __launch_bounds__(kBlock) void factor_sparse_kernel(FactorArgs<T> a) 
             const double bl = (double)group_bcast<P, rl>(bv[pl]);
             static_for<0, R>([&](auto PI) {
                 constexpr int p = PI;
-                const T val = cov_r2<KIND>(sqdist3(c0[p], c1[p], c2[p], y0, y1, y2), a.cov);
+                const T val = cov_r2<KIND>(sqdist3(c0[p], c1[p], c2[p], y0, y1, y2), cov);
                 const bool keep = (ok[p] & okl & (int)(l != p * P + r)) != 0;
                 res[p] = fma(-(double)(keep ? val : T(0)), bl, res[p]);
             });
@@ -232,12 +261,38 @@ __global__ __launch_bounds__(kBlock) void factor_sparse_kernel(FactorArgs<T> a) 
             bv[p] = bv[p] + dz[p];
             kb = fma((double)kc[p], (double)bv[p], kb);
         });
-        s2 = a.diag - group_sum<P>(kb);
+        s2 = diag - group_sum<P>(kb);
     }
     bad |= !(s2 > 0.0);
+    s2_out = s2;
+    minpiv_out = minpiv;
+    bad_out = bad;
+}
 
-    // ---- outputs
-    if (live) {
+// One group of P lanes per sparse point, all points at once.  FP32 storage
+// (REFINE): a point whose pivots fail or fall below redo_ratio * K_ii is not
+// written here; it is appended to the redo list and recomputed in double by
+// factor_redo_kernel.
+template <typename T, int K, int P, int KIND, bool REFINE>
+__global__ __launch_bounds__(kBlock) void factor_sparse_kernel(FactorArgs<T> a) {
+    static_assert(K % P == 0, "K must be a multiple of P");
+    constexpr int R = K / P;
+    constexpr int PTS = kBlock / P;
+    const int tid = threadIdx.x;
+    const int r = tid % P;
+    const int64_t blk = xcd_block(blockIdx.x, a.nblocks);
+    const int64_t sp_raw = blk * PTS + tid / P;
+    const bool live = sp_raw < a.ns;
+    const int64_t sp = live ? sp_raw : a.ns - 1;      // dead lanes mirror a live point
+    const int64_t base = (sp >> 6) * (int64_t)K * kTile + (sp & 63);
+
+    T bv[R];
+    double s2, minpiv;
+    bool bad;
+    factor_point<T, T, K, P, KIND, REFINE>(a.x, a.nbr, a.n0, sp, r, a.cov, a.diag, bv, s2, minpiv, bad);
+    const bool redo = REFINE && (bad || minpiv < a.redo_ratio * a.diag);
+
+    if (live && !redo) {
         static_for<0, R>([&](auto PI) {
             constexpr int p = PI;
             a.b[base + (int64_t)(p * P + r) * kTile] = bv[p];
@@ -250,7 +305,11 @@ __global__ __launch_bounds__(kBlock) void factor_sparse_kernel(FactorArgs<T> a) 
             }
         }
     }
-    double lsum = (live && r == 0) ? 0.5 * log(s2) : 0.0;
+    if (live && redo && r == 0) {
+        const unsigned long long slot = atomicAdd((unsigned long long*)&a.status[2], 1ull);
+        a.redo[slot] = (uint32_t)sp;
+    }
+    double lsum = (live && !redo && r == 0) ? 0.5 * log(s2) : 0.0;
     lsum = wave_sum_f64<T>(lsum);
     __shared__ double part[kBlock / 64];
     if ((tid & 63) == 0) part[tid >> 6] = lsum;
@@ -259,6 +318,42 @@ __global__ __launch_bounds__(kBlock) void factor_sparse_kernel(FactorArgs<T> a) 
         double s = 0.0;
         for (int w = 0; w < kBlock / 64; ++w) s += part[w];
         a.ldpart[blk] = s;
+    }
+}
+
+// FP32 storage: the listed points again, entirely in double (kernel values,
+// Cholesky, solves), results rounded to float.  A fixed grid walks the list;
+// log sigma of these points is added in fixed point to status[3].
+template <int K, int KIND>
+__global__ __launch_bounds__(kBlock) void factor_redo_kernel(FactorArgs<float> a, Cov<double> cov) {
+    constexpr int P = factor_lanes(VECCHIA_FP64, K);
+    constexpr int R = K / P;
+    constexpr int PTS = kBlock / P;
+    const int tid = threadIdx.x;
+    const int r = tid % P;
+    const int64_t count = (int64_t)a.status[2];
+    const int64_t groups = (int64_t)gridDim.x * PTS;
+    for (int64_t e = (int64_t)blockIdx.x * PTS + tid / P; e < count; e += groups) {
+        const int64_t sp = a.redo[e];
+        const int64_t base = (sp >> 6) * (int64_t)K * kTile + (sp & 63);
+        double bv[R];
+        double s2, minpiv;
+        bool bad;
+        factor_point<double, float, K, P, KIND, false>(a.x, a.nbr, a.n0, sp, r, cov, a.diag, bv, s2, minpiv, bad);
+        static_for<0, R>([&](auto PI) {
+            constexpr int p = PI;
+            a.b[base + (int64_t)(p * P + r) * kTile] = (float)bv[p];
+        });
+        if (r == 0) {
+            a.sigma[sp] = (float)sqrt(s2);
+            if (bad) {
+                atomicMin((unsigned long long*)&a.status[0], (unsigned long long)(a.n0 + sp));
+                atomicAdd((unsigned long long*)&a.status[1], 1ull);
+            } else {
+                const long long fix = __double2ll_rn(0.5 * log(s2) * kFixScale);
+                atomicAdd((unsigned long long*)&a.status[3], (unsigned long long)fix);
+            }
+        }
     }
 }
 
@@ -273,17 +368,28 @@ hipError_t launch_factor_sparse_t(const FactorLaunch& L, hipStream_t stream) {
     a.sigma = static_cast<T*>(L.sigma);
     a.ldpart = L.ldpart;
     a.status = L.status;
+    a.redo = L.redo;
     a.ns = L.ns;
     a.n0 = L.n0;
     a.cov = make_cov<T>(L.kern);
     a.diag = L.kern.sigma * L.kern.sigma + L.kern.nugget;
+    a.redo_ratio = L.redo_ratio;
     const int64_t pts = kBlock / P;
     a.nblocks = (L.ns + pts - 1) / pts;
     if (a.nblocks == 0) return hipSuccess;
     constexpr bool refine = sizeof(T) == 4;
     hipLaunchKernelGGL((factor_sparse_kernel<T, K, P, KIND, refine>), dim3((unsigned)a.nblocks), dim3(kBlock), 0,
                        stream, a);
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !refine) return e;
+    if constexpr (refine) {
+        constexpr int P64 = factor_lanes(VECCHIA_FP64, K);
+        const int64_t blocks = std::min<int64_t>((a.nblocks * P64 + P - 1) / P, 1024);
+        hipLaunchKernelGGL((factor_redo_kernel<K, KIND>), dim3((unsigned)blocks), dim3(kBlock), 0, stream, a,
+                           make_cov<double>(L.kern));
+        e = hipGetLastError();
+    }
+    return e;
 }
 
 }  // namespace vk

@@ -151,7 +151,7 @@ class Factor:
     """One factored point set: b, sigma, L0 and logdet partials in a
     device workspace, produced by ``vecchia_factor`` on the current stream."""
 
-    def __init__(self, dg, kernel, workspace=None):
+    def __init__(self, dg, kernel, workspace=None, redo_log2=0):
         self._lib = _lib.load()
         self.dg = dg
         self.kernel = kernel
@@ -163,6 +163,7 @@ class Factor:
         self.workspace = workspace
         v = _lib.ViewStruct()
         v.n, v.k, v.kp, v.n0, v.n_levels, v.precision = dg.n, dg.k, dg.kp, dg.n0, dg.n_levels, dg.precision
+        v.redo_log2 = int(redo_log2)
         v.x = dg.x.data_ptr()
         v.nbr = dg.nbr.data_ptr()
         v.level_ptr = dg.level_ptr.ctypes.data
@@ -172,8 +173,16 @@ class Factor:
         v.workspace_bytes = workspace.numel()
         self.view = v
         self._kc = kernel.to_c()
-        _lib.check(self._lib.vecchia_factor(ctypes.byref(self.view), ctypes.byref(self._kc), _stream(dg.device)),
-                   "vecchia_factor")
+        self.refactor()
+
+    def refactor(self, kernel=None):
+        """Run vecchia_factor again (optionally with new kernel parameters)
+        into the same workspace."""
+        if kernel is not None:
+            self.kernel = kernel
+            self._kc = kernel.to_c()
+        _lib.check(self._lib.vecchia_factor(ctypes.byref(self.view), ctypes.byref(self._kc),
+                                            _stream(self.dg.device)), "vecchia_factor")
 
     def _vec(self, t, name):
         if not isinstance(t, torch.Tensor) or t.device != self.dg.device or t.dtype != self.dg.dtype \
@@ -220,6 +229,41 @@ class Factor:
                    "vecchia_status")
         return None
 
+    def backward(self, xi, v, v_bar=None, xi_bar_in=None, logdet_bar=0.0, scratch=None):
+        """Reverse-mode derivatives of <v_bar, F xi> + <xi_bar_in, F^-1 v> +
+        logdet_bar * logdet.  (xi, v) is the forward pair.  Returns
+        (xi_bar or None, v_bar_out or None, theta_bar) with theta_bar a float64
+        device tensor [d/dsigma, d/dell].  Needs a DeviceGraph built with
+        with_children=True."""
+        if self.dg.child_ptr is None:
+            raise ValueError("backward needs the children lists: to_device(..., with_children=True)")
+        xi = self._vec(xi, "xi")
+        v = self._vec(v, "v")
+        vb = self._vec(v_bar, "v_bar") if v_bar is not None else None
+        xb = self._vec(xi_bar_in, "xi_bar_in") if xi_bar_in is not None else None
+        xi_bar = torch.empty_like(xi) if vb is not None else None
+        v_bar_out = torch.empty_like(v) if xb is not None else None
+        theta = torch.empty(2, dtype=torch.float64, device=self.dg.device)
+        nbytes = ctypes.c_size_t()
+        _lib.check(self._lib.vecchia_backward_scratch_bytes(ctypes.byref(self.view), ctypes.byref(nbytes)),
+                   "vecchia_backward_scratch_bytes")
+        if scratch is None or scratch.numel() < nbytes.value:
+            scratch = torch.empty(nbytes.value, dtype=torch.uint8, device=self.dg.device)
+        ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+        _lib.check(self._lib.vecchia_backward(ctypes.byref(self.view), ctypes.byref(self._kc), ptr(xi), ptr(v),
+                                              ptr(vb), ptr(xb), float(logdet_bar), ptr(xi_bar), ptr(v_bar_out),
+                                              ptr(theta), ptr(scratch), scratch.numel(), _stream(self.dg.device)),
+                   "vecchia_backward")
+        return xi_bar, v_bar_out, theta
+
+    def counts(self):
+        """(points with a non-positive pivot or variance, points recomputed in
+        double on the FP32 path) of the last factorisation; synchronises."""
+        bad, redo = ctypes.c_int64(), ctypes.c_int64()
+        _lib.check(self._lib.vecchia_factor_counts(ctypes.byref(self.view), _stream(self.dg.device),
+                                                   ctypes.byref(bad), ctypes.byref(redo)), "vecchia_factor_counts")
+        return bad.value, redo.value
+
     def first_bad_slot(self):
         bad = ctypes.c_int64()
         rc = self._lib.vecchia_status(ctypes.byref(self.view), _stream(self.dg.device), ctypes.byref(bad))
@@ -246,6 +290,15 @@ class Factor:
     def dg_ntiles(self):
         return (self.dg.n - self.dg.n0 + 63) // 64
 
+    def coefficient_rows(self, rows):
+        """(b (len(rows), kp), sigma (len(rows),)) of the given sparse indices,
+        gathered on the device and copied to the host."""
+        rows = torch.as_tensor(np.asarray(rows, dtype=np.int64), device=self.dg.device)
+        nt, kp = self.dg_ntiles(), self.dg.kp
+        b = self._ws_slice("b").view(nt, kp, 64)[rows // 64, :, rows % 64]
+        s = self._ws_slice("sigma")[rows]
+        return b.cpu().numpy(), s.cpu().numpy()
+
     def coefficients(self):
         """(b as (Ns, kp) in sparse-index order, sigma (Ns,)) copied to the host."""
         nt, kp, ns = self.dg_ntiles(), self.dg.kp, self.dg.n - self.dg.n0
@@ -271,3 +324,26 @@ def _layout(dg):
     off = _align(off + ntiles * 64 * esz)
     lay["l0"] = off
     return lay
+
+
+def profile_enable(on=True):
+    """Per-kernel HIP-event timing inside the library (adds two event records
+    per launch on the launch stream)."""
+    lib = _lib.load()
+    _lib.check(lib.vecchia_profile_enable(1 if on else 0), "vecchia_profile_enable")
+
+
+def profile_reset():
+    _lib.check(_lib.load().vecchia_profile_reset(), "vecchia_profile_reset")
+
+
+def profile_read(max_kernels=64):
+    """{kernel name: (total milliseconds, launches)}; synchronises the device."""
+    lib = _lib.load()
+    names = ctypes.create_string_buffer(8192)
+    ms = (ctypes.c_double * max_kernels)()
+    cnt = (ctypes.c_int64 * max_kernels)()
+    nk = ctypes.c_int32()
+    _lib.check(lib.vecchia_profile_read(names, 8192, ms, cnt, max_kernels, ctypes.byref(nk)), "vecchia_profile_read")
+    keys = names.value.decode().split("\n")[:nk.value]
+    return {k: (ms[i], cnt[i]) for i, k in enumerate(keys)}

@@ -17,12 +17,12 @@ def rel_err(a, ref):
 class Run:
     """Build the graph, upload, factor, forward(xi), inverse(v) on the GPU."""
 
-    def __init__(self, x, k, n0, kern, precision, xi_input=None, device="cuda:0"):
+    def __init__(self, x, k, n0, kern, precision, xi_input=None, device="cuda:0", redo_log2=0):
         self.g = Graph(x, k, n0)
         self.kern = kern
         self.precision = precision
         self.dg = self.g.to_device(precision, device)
-        self.fac = Factor(self.dg, KernelParams(kern.kind, kern.sigma, kern.ell, kern.nugget))
+        self.fac = Factor(self.dg, KernelParams(kern.kind, kern.sigma, kern.ell, kern.nugget), redo_log2=redo_log2)
         self.dtype = torch.float64 if precision == FP64 else torch.float32
         self.xi_input = xi_input
         if xi_input is not None:
