@@ -207,6 +207,73 @@ int vecchia_factor_counts(const vecchia_view* view, void* stream, int64_t* not_p
  * none; the dense block reports its first bad pivot row). */
 int vecchia_status(const vecchia_view* view, void* stream, int64_t* first_bad_slot);
 
+/* ---- serving: continuous batching of requests on one GPU ----------------- */
+/* Not a passage of the paper: a request loop around the calls above.  Each
+ * request brings its own points (host, N x 3 doubles, input order), kernel,
+ * k, n0 and one operation; the engine builds its graph on a host worker
+ * thread, admits it when its whole device footprint fits in the free part of
+ * the caller's HBM arena (FIFO in the order graphs become ready, so a slow
+ * build does not block the requests behind it), runs upload + vecchia_factor + the
+ * operation + download on one of its streams, and frees the arena range at
+ * completion.  Requests on different streams overlap on the device.  All
+ * computation is FP32 (VECCHIA_FP32).  Thread safety: one thread drives a
+ * server (submit/progress/take/result/release); graph workers are internal. */
+#define VECCHIA_OP_FORWARD 0   /* result = F(input), input = white noise, input order */
+#define VECCHIA_OP_INVERSE 1   /* result = F^-1(input), input = field values */
+#define VECCHIA_OP_LOGDET  2   /* result = log det (no input) */
+
+typedef struct vecchia_server vecchia_server;
+
+typedef struct vecchia_serve_stats {
+    size_t arena_bytes, bytes_in_use, peak_bytes, largest_free;
+    int64_t building, queued, running, admitted, completed, failed, rejected, cancelled;
+} vecchia_serve_stats;
+
+/* arena: (device) 256-byte aligned buffer of arena_bytes owned by the caller
+ * and not touched by it while the server lives (the HBM budget).  n_streams
+ * in 1..64 (default priority), graph_workers host threads each running
+ * graph_build with graph_threads threads.  mock != 0: no device calls at all
+ * (arena may be NULL); a running request completes after 3 serve_progress
+ * calls and returns its input (host tests of the scheduler). */
+int serve_create(void* arena, size_t arena_bytes, int32_t n_streams, int32_t graph_workers, int32_t graph_threads,
+                 int32_t mock, vecchia_server** out);
+
+/* Device bytes a request of N points needs (coordinates, tiled neighbours,
+ * workspace, input, output). */
+int serve_request_bytes(int64_t n, int32_t k, int32_t n0, size_t* bytes);
+
+/* Copies x (host, N x 3) and input (host, N floats, input order; NULL for
+ * logdet) and queues the request.  EBUDGET if it can never fit in the arena;
+ * EINVAL on bad arguments.  *id > 0 identifies the request. */
+int serve_submit(vecchia_server* s, const double* x, int64_t n, int32_t k, int32_t n0, const vecchia_kernel* kern,
+                 int32_t op, const float* input, int64_t* id);
+
+/* Non-blocking step of the engine: retires finished requests (frees their
+ * arena ranges), admits queued ones in FIFO order while the head fits, and
+ * enqueues their device work.  *n_completed = requests waiting in serve_take. */
+int serve_progress(vecchia_server* s, int32_t* n_completed);
+
+/* Pops the id of one finished request (0 if none). */
+int serve_take(vecchia_server* s, int64_t* id);
+
+/* Result of a finished request: out (host, N floats, input order) for
+ * forward/inverse, *logdet for logdet; times[4] (seconds) = graph build,
+ * queue wait, device time (admission to completion), total.  Returns the
+ * request's own error if it failed. */
+int serve_result(vecchia_server* s, int64_t id, float* out, double* logdet, double* times);
+
+/* Frees the host copies of a finished or cancelled request. */
+int serve_release(vecchia_server* s, int64_t id);
+
+/* Cancels a request that is not yet admitted. */
+int serve_cancel(vecchia_server* s, int64_t id);
+
+int serve_stats(vecchia_server* s, vecchia_serve_stats* out);
+
+/* Waits for the device work in flight, stops the workers, frees everything
+ * except the caller's arena. */
+void serve_destroy(vecchia_server* s);
+
 /* Padded width used for a neighbour count k (8, 16 or 32), or -1. */
 int32_t vecchia_padded_k(int32_t k);
 

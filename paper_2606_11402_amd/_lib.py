@@ -34,6 +34,13 @@ class KernelStruct(ctypes.Structure):
     _fields_ = [("kind", c_int32), ("sigma", c_double), ("ell", c_double), ("nugget", c_double)]
 
 
+class ServeStats(ctypes.Structure):
+    _fields_ = [("arena_bytes", c_size_t), ("bytes_in_use", c_size_t), ("peak_bytes", c_size_t),
+                ("largest_free", c_size_t), ("building", c_int64), ("queued", c_int64), ("running", c_int64),
+                ("admitted", c_int64), ("completed", c_int64), ("failed", c_int64), ("rejected", c_int64),
+                ("cancelled", c_int64)]
+
+
 class ViewStruct(ctypes.Structure):
     _fields_ = [
         ("n", c_int64), ("k", c_int32), ("kp", c_int32), ("n0", c_int32), ("n_levels", c_int32),
@@ -68,6 +75,17 @@ _SIGNATURES = {
     "vecchia_profile_read": (c_int32, [ctypes.c_char_p, c_size_t, P(c_double), P(c_int64), c_int32, P(c_int32)]),
     "vecchia_profile_reset": (c_int32, []),
     "vecchia_abi_sizes": (c_int32, [P(c_size_t), P(c_size_t)]),
+    "serve_create": (c_int32, [c_void_p, c_size_t, c_int32, c_int32, c_int32, c_int32, P(c_void_p)]),
+    "serve_request_bytes": (c_int32, [c_int64, c_int32, c_int32, P(c_size_t)]),
+    "serve_submit": (c_int32, [c_void_p, c_void_p, c_int64, c_int32, c_int32, P(KernelStruct), c_int32, c_void_p,
+                               P(c_int64)]),
+    "serve_progress": (c_int32, [c_void_p, P(c_int32)]),
+    "serve_take": (c_int32, [c_void_p, P(c_int64)]),
+    "serve_result": (c_int32, [c_void_p, c_int64, c_void_p, P(c_double), P(c_double)]),
+    "serve_release": (c_int32, [c_void_p, c_int64]),
+    "serve_cancel": (c_int32, [c_void_p, c_int64]),
+    "serve_stats": (c_int32, [c_void_p, P(ServeStats)]),
+    "serve_destroy": (None, [c_void_p]),
     "vecchia_last_error": (ctypes.c_char_p, []),
     "vecchia_version": (ctypes.c_char_p, []),
 }

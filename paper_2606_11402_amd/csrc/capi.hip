@@ -59,9 +59,9 @@ hipError_t timed(const char* name, hipStream_t s, F&& launch) {
         b = take_event();
     }
     if (!a || !b) return launch();
-    hipEventRecord(a, s);
+    (void)hipEventRecord(a, s);
     hipError_t err = launch();
-    hipEventRecord(b, s);
+    (void)hipEventRecord(b, s);
     std::lock_guard<std::mutex> lk(g_prof_mu);
     g_pending.push_back(Pending{name, a, b});
     return err;

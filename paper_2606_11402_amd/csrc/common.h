@@ -59,22 +59,30 @@ inline Layout workspace_layout(int64_t n, int kp, int n0, int precision) {
     return w;
 }
 
-// Covariance parameters, pre-scaled on the host.
+// Covariance parameters, pre-scaled on the host.  The e_* constants carry a
+// factor log2(e) so that float kernel values use the hardware exp2.
 template <typename T>
 struct Cov {
     T s2;          // sigma^2
     T inv_ell;     // 1/ell
     T c_m32;       // sqrt(3)/ell
     T c_se;        // -1/(2 ell^2)
+    T e_exp;       // -log2(e)/ell
+    T e_m32;       // -sqrt(3) log2(e)/ell
+    T e_se;        // -log2(e)/(2 ell^2)
 };
 
 template <typename T>
 inline Cov<T> make_cov(const vecchia_kernel& k) {
+    const double log2e = 1.4426950408889634, sqrt3 = 1.7320508075688772;
     Cov<T> c;
     c.s2 = (T)(k.sigma * k.sigma);
     c.inv_ell = (T)(1.0 / k.ell);
-    c.c_m32 = (T)(1.7320508075688772 / k.ell);
+    c.c_m32 = (T)(sqrt3 / k.ell);
     c.c_se = (T)(-0.5 / (k.ell * k.ell));
+    c.e_exp = (T)(-log2e / k.ell);
+    c.e_m32 = (T)(-sqrt3 * log2e / k.ell);
+    c.e_se = (T)(-0.5 * log2e / (k.ell * k.ell));
     return c;
 }
 
@@ -86,21 +94,29 @@ __device__ __forceinline__ double rsqrt_f64(double d) {
     return fma(0.5 * y0, e, y0);
 }
 
-__device__ __forceinline__ float dev_exp(float x) { return expf(x); }
-__device__ __forceinline__ double dev_exp(double x) { return exp(x); }
-__device__ __forceinline__ float dev_sqrt(float x) { return sqrtf(x); }
-__device__ __forceinline__ double dev_sqrt(double x) { return sqrt(x); }
-
-// kappa(r) from the squared distance r2 (no nugget).
-template <int KIND, typename T>
-__device__ __forceinline__ T cov_r2(T r2, const Cov<T>& c) {
+// kappa(r) from the squared distance r2 (no nugget).  Float: hardware exp2
+// and square root (about 1 ulp each); double: the device math library.
+template <int KIND>
+__device__ __forceinline__ float cov_r2(float r2, const Cov<float>& c) {
     if constexpr (KIND == 0) {
-        return c.s2 * dev_exp(-dev_sqrt(r2) * c.inv_ell);
+        return c.s2 * __builtin_amdgcn_exp2f(__builtin_amdgcn_sqrtf(r2) * c.e_exp);
     } else if constexpr (KIND == 1) {
-        const T a = dev_sqrt(r2) * c.c_m32;
-        return c.s2 * (T(1) + a) * dev_exp(-a);
+        const float t = __builtin_amdgcn_sqrtf(r2) * c.e_m32;            // -a log2(e)
+        return c.s2 * __builtin_fmaf(t, -0.6931471805599453f, 1.0f) * __builtin_amdgcn_exp2f(t);
     } else {
-        return c.s2 * dev_exp(r2 * c.c_se);
+        return c.s2 * __builtin_amdgcn_exp2f(r2 * c.e_se);
+    }
+}
+
+template <int KIND>
+__device__ __forceinline__ double cov_r2(double r2, const Cov<double>& c) {
+    if constexpr (KIND == 0) {
+        return c.s2 * exp(-sqrt(r2) * c.inv_ell);
+    } else if constexpr (KIND == 1) {
+        const double a = sqrt(r2) * c.c_m32;
+        return c.s2 * (1.0 + a) * exp(-a);
+    } else {
+        return c.s2 * exp(r2 * c.c_se);
     }
 }
 

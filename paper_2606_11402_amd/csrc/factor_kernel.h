@@ -101,8 +101,11 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
     return v;
 }
 
-// Coordinates of the neighbours of the rows this lane owns (-1 padded rows
-// read point 0 and are masked by ok).
+// Coordinates of the neighbours of the rows this lane owns.  A padded slot
+// (-1) is placed at its own far-away point (1e15 (m+1), 0, 0): its kernel
+// values with every other point, real or padded, are exactly 0, so it acts
+// as an identity row and column of K_cc without any masking in the
+// evaluation loops (the squared distances, >= 1e30, stay finite in float).
 template <typename T, typename TX, int K, int P>
 __device__ __forceinline__ void gather_rows(const TX* __restrict__ x, const int32_t* __restrict__ nbr, int64_t base,
                                             int r, T* c0, T* c1, T* c2, int* ok) {
@@ -112,28 +115,30 @@ __device__ __forceinline__ void gather_rows(const TX* __restrict__ x, const int3
         const int32_t j = nbr[base + (int64_t)(p * P + r) * kTile];
         ok[p] = j >= 0;
         const int64_t jj = j >= 0 ? j : 0;
-        c0[p] = (T)x[jj * 3 + 0];
-        c1[p] = (T)x[jj * 3 + 1];
-        c2[p] = (T)x[jj * 3 + 2];
+        const T far = (T)(1e15 * (double)(p * P + r + 1));
+        c0[p] = j >= 0 ? (T)x[jj * 3 + 0] : far;
+        c1[p] = j >= 0 ? (T)x[jj * 3 + 1] : T(0);
+        c2[p] = j >= 0 ? (T)x[jj * 3 + 2] : T(0);
     });
 }
 
-// Strictly lower part of K_cc into A (diagonal slots and padded rows zero).
+// K_cc into the lane's row blocks.  Entries on and above the diagonal of a
+// row block receive finite kernel values too; the Cholesky zeroes them when
+// their column is reached, so they never act as multipliers.
 template <typename T, int K, int P, int KIND>
 __device__ __forceinline__ void assemble_kcc(const T* c0, const T* c1, const T* c2, const int* ok, int r,
                                              const Cov<T>& cov, T* A) {
     constexpr int R = K / P;
+    (void)ok;
+    (void)r;
     static_for<0, K>([&](auto LI) {
         constexpr int l = LI, pl = l / P, rl = l % P;
         const T y0 = group_bcast<P, rl>(c0[pl]);
         const T y1 = group_bcast<P, rl>(c1[pl]);
         const T y2 = group_bcast<P, rl>(c2[pl]);
-        const int okl = group_bcast<P, rl>(ok[pl]);
         static_for<pl, R>([&](auto PI) {
             constexpr int p = PI;
-            const T val = cov_r2<KIND>(sqdist3(c0[p], c1[p], c2[p], y0, y1, y2), cov);
-            const bool keep = (ok[p] & okl & (int)(l < p * P + r)) != 0;
-            A[row_off<P>(p) + l] = keep ? val : T(0);
+            A[row_off<P>(p) + l] = cov_r2<KIND>(sqdist3(c0[p], c1[p], c2[p], y0, y1, y2), cov);
         });
     });
 }
@@ -199,8 +204,7 @@ __device__ __forceinline__ void factor_point(const TX* __restrict__ x, const int
     double Dg[R];
     static_for<0, R>([&](auto PI) {
         constexpr int p = PI;
-        const T val = cov_r2<KIND>(sqdist3(c0[p], c1[p], c2[p], t0, t1, t2), cov);
-        kc[p] = ok[p] ? val : T(0);
+        kc[p] = cov_r2<KIND>(sqdist3(c0[p], c1[p], c2[p], t0, t1, t2), cov);
         Dg[p] = ok[p] ? diag : 1.0;
     });
 
@@ -233,22 +237,23 @@ __device__ __forceinline__ void factor_point(const TX* __restrict__ x, const int
 #pragma unroll
         for (int p = 0; p < R; ++p) asm volatile("" : "+v"(c0[p]), "+v"(c1[p]), "+v"(c2[p]) : "v"(bv[0]));
         double res[R];
+        // kappa(0) b_i enters through the l = i term of the loop; the nugget
+        // part of K_ii is added here (a padded row has b_i = 0).
+        const double nug = diag - (double)cov.s2;
         static_for<0, R>([&](auto PI) {
             constexpr int p = PI;
-            res[p] = (double)kc[p] - (ok[p] ? diag : 1.0) * (double)bv[p];
+            res[p] = (double)kc[p] - nug * (double)bv[p];
         });
         static_for<0, K>([&](auto LI) {
             constexpr int l = LI, pl = l / P, rl = l % P;
             const T y0 = group_bcast<P, rl>(c0[pl]);
             const T y1 = group_bcast<P, rl>(c1[pl]);
             const T y2 = group_bcast<P, rl>(c2[pl]);
-            const int okl = group_bcast<P, rl>(ok[pl]);
             const double bl = (double)group_bcast<P, rl>(bv[pl]);
             static_for<0, R>([&](auto PI) {
                 constexpr int p = PI;
                 const T val = cov_r2<KIND>(sqdist3(c0[p], c1[p], c2[p], y0, y1, y2), cov);
-                const bool keep = (ok[p] & okl & (int)(l != p * P + r)) != 0;
-                res[p] = fma(-(double)(keep ? val : T(0)), bl, res[p]);
+                res[p] = fma(-(double)val, bl, res[p]);
             });
         });
         T dz[R];
@@ -273,8 +278,12 @@ __device__ __forceinline__ void factor_point(const TX* __restrict__ x, const int
 // (REFINE): a point whose pivots fail or fall below redo_ratio * K_ii is not
 // written here; it is appended to the redo list and recomputed in double by
 // factor_redo_kernel.
+#ifndef VK_FACTOR_MIN_WAVES
+#define VK_FACTOR_MIN_WAVES 2   // waves per SIMD the register allocation must allow
+#endif
+
 template <typename T, int K, int P, int KIND, bool REFINE>
-__global__ __launch_bounds__(kBlock) void factor_sparse_kernel(FactorArgs<T> a) {
+__global__ __launch_bounds__(kBlock, VK_FACTOR_MIN_WAVES) void factor_sparse_kernel(FactorArgs<T> a) {
     static_assert(K % P == 0, "K must be a multiple of P");
     constexpr int R = K / P;
     constexpr int PTS = kBlock / P;

@@ -1,4 +1,7 @@
 // Cross-lane helpers for point groups of P consecutive lanes of a wave64.
+// Every lane of the wave is active where these are used and every lane is
+// written (row and bank masks 0xF, bound control on), so no old value is
+// needed.
 //
 // A group of P lanes (P = 1, 2, 4 or 8) works on one point; lane r of the
 // group owns matrix rows i = p*P + r.  Values owned by another lane of the
@@ -32,10 +35,10 @@ __device__ __forceinline__ int group_bcast_i32(int v) {
     } else if constexpr (P == 2) {
         // pairs (0,1), (2,3) inside each quad
         constexpr int ctrl = (S) | (S << 2) | ((2 + S) << 4) | ((2 + S) << 6);
-        return __builtin_amdgcn_update_dpp(0, v, ctrl, 0xF, 0xF, false);
+        return __builtin_amdgcn_mov_dpp(v, ctrl, 0xF, 0xF, true);
     } else if constexpr (P == 4) {
         constexpr int ctrl = S | (S << 2) | (S << 4) | (S << 6);
-        return __builtin_amdgcn_update_dpp(0, v, ctrl, 0xF, 0xF, false);
+        return __builtin_amdgcn_mov_dpp(v, ctrl, 0xF, 0xF, true);
     } else {
         // bit mode: lane' = (lane & and_mask) | or_mask, within 32 lanes
         constexpr int pattern = 0x18 | (S << 5);
@@ -47,9 +50,9 @@ __device__ __forceinline__ int group_bcast_i32(int v) {
 template <int X>
 __device__ __forceinline__ int group_xor_i32(int v) {
     if constexpr (X == 1) {
-        return __builtin_amdgcn_update_dpp(0, v, 1 | (0 << 2) | (3 << 4) | (2 << 6), 0xF, 0xF, false);
+        return __builtin_amdgcn_mov_dpp(v, 1 | (0 << 2) | (3 << 4) | (2 << 6), 0xF, 0xF, true);
     } else if constexpr (X == 2) {
-        return __builtin_amdgcn_update_dpp(0, v, 2 | (3 << 2) | (0 << 4) | (1 << 6), 0xF, 0xF, false);
+        return __builtin_amdgcn_mov_dpp(v, 2 | (3 << 2) | (0 << 4) | (1 << 6), 0xF, 0xF, true);
     } else {
         static_assert(X == 4, "xor distance");
         return __builtin_amdgcn_ds_swizzle(v, 0x1F | (4 << 10));

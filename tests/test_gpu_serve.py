@@ -1,0 +1,79 @@
+"""Serving engine on the GPU: results are identical alone and in a mix of
+concurrent requests, agree with the direct calls and with the oracle, and
+the engine overlaps requests within its HBM budget."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from paper_2606_11402_amd import FP32, Factor, Graph, KernelParams
+from paper_2606_11402_amd.serve import Server
+
+pytestmark = pytest.mark.gpu
+
+
+def make_requests(seed=7, count=24):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n = int(10 ** rng.uniform(3, 5.3))
+        k = int(rng.choice([8, 16, 32]))
+        ell = float(rng.uniform(0.01, 0.2))
+        op = str(rng.choice(["forward", "inverse", "logdet"]))
+        x = workloads.as_fp32_exact(workloads.uniform(n, 7000 + i))
+        inp = None if op == "logdet" else workloads.white_noise(n, 7100 + i).astype(np.float32)
+        out.append((x, k, ell, op, inp))
+    return out
+
+
+def submit(srv, req):
+    x, k, ell, op, inp = req
+    return srv.submit(x, k, 1, 1.0, ell, op, inp)
+
+
+def test_alone_and_in_the_mix_are_identical():
+    reqs = make_requests()
+    budget = 3 * Server.request_bytes(200000, 32)
+    alone = {}
+    for j in (0, 5, 11, 23):
+        srv = Server(budget, n_streams=4, graph_workers=4)
+        rid = submit(srv, reqs[j])
+        alone[j] = srv.drain()[rid][0]
+        srv.close()
+    srv = Server(budget, n_streams=4, graph_workers=8)
+    ids = [submit(srv, r) for r in reqs]
+    res = srv.drain()
+    st = srv.stats()
+    srv.close()
+    for j, ref in alone.items():
+        got = res[ids[j]][0]
+        if reqs[j][3] == "logdet":
+            assert got == ref
+        else:
+            assert np.array_equal(got, ref)
+    single_max = max(Server.request_bytes(len(r[0]), r[1]) for r in reqs)
+    assert st["peak_bytes"] > single_max          # several requests were resident at once
+    assert st["peak_bytes"] <= budget and st["failed"] == 0
+
+
+def test_served_results_match_direct_calls_and_oracle():
+    n, k, ell = 3000, 16, 0.1
+    x = workloads.as_fp32_exact(workloads.uniform(n, 8001))
+    xi = workloads.white_noise(n, 8101).astype(np.float32)
+    srv = Server(1 << 28, n_streams=2, graph_workers=2)
+    a = srv.submit(x, k, 1, 1.0, ell, "forward", xi)
+    b = srv.submit(x, k, 1, 1.0, ell, "logdet")
+    res = srv.drain()
+    srv.close()
+    v_srv, ld_srv = res[a][0], res[b][0]
+    g = Graph(x, k, 128)
+    fac = Factor(g.to_device(FP32, "cuda:0"), KernelParams(1, 1.0, ell))
+    v_dir = fac.forward(torch.from_numpy(g.to_storage(xi)).cuda()).cpu().numpy()
+    assert np.array_equal(v_srv, g.from_storage(v_dir))
+    og = oracle.build_graph(x, k, 128)
+    of = oracle.factor(og, oracle.Kernel(1, 1.0, ell))
+    v_or = np.empty(n)
+    v_or[og.perm] = oracle.forward(og, of, xi.astype(np.float64)[og.perm])
+    assert np.max(np.abs(v_srv - v_or)) / np.max(np.abs(v_or)) <= 1e-4
+    assert abs(ld_srv - oracle.logdet(of)) <= 1e-4 * abs(oracle.logdet(of))
