@@ -145,6 +145,9 @@ typedef struct vecchia_view {
     const void* x;             /* (device) N x 3 coordinates in storage order, double or float */
     const int32_t* nbr;        /* (device) tiled neighbour indices (graph_export_nbr layout 1) */
     const int32_t* level_ptr;  /* (host)   L + 2 batch boundaries (graph_export) */
+    const int32_t* level_ptr_dev; /* (device) the same L + 2 boundaries, or NULL.  When set, runs of
+                                     consecutive small batches of the forward pass are processed by one
+                                     workgroup in a single launch instead of one launch per batch. */
     const int64_t* child_ptr;  /* (device) N + 1, only needed by vecchia_backward, else NULL */
     const int32_t* child;      /* (device) packed children, only for vecchia_backward, else NULL */
     void* workspace;           /* (device) vecchia_workspace_bytes() bytes, 256-byte aligned */

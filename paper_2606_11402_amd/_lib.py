@@ -45,7 +45,8 @@ class ViewStruct(ctypes.Structure):
     _fields_ = [
         ("n", c_int64), ("k", c_int32), ("kp", c_int32), ("n0", c_int32), ("n_levels", c_int32),
         ("precision", c_int32), ("redo_log2", c_int32),
-        ("x", c_void_p), ("nbr", c_void_p), ("level_ptr", c_void_p), ("child_ptr", c_void_p),
+        ("x", c_void_p), ("nbr", c_void_p), ("level_ptr", c_void_p), ("level_ptr_dev", c_void_p),
+        ("child_ptr", c_void_p),
         ("child", c_void_p), ("workspace", c_void_p), ("workspace_bytes", c_size_t),
         ("kernel", KernelStruct),
     ]

@@ -50,6 +50,68 @@ __global__ __launch_bounds__(kBlock) void apply_kernel(const int32_t* __restrict
     }
 }
 
+// A run of consecutive small batches [l_begin, l_end) in one workgroup: the
+// batches are processed in order with a workgroup barrier between them (the
+// barrier orders the global writes of batch l before the gathers of batch
+// l + 1 inside the workgroup), which replaces one launch per batch.
+template <typename T, int KP>
+__global__ __launch_bounds__(kRunThreads) void forward_run_kernel(const int32_t* __restrict__ nbr,
+                                                                  const T* __restrict__ b, const T* __restrict__ sig,
+                                                                  const T* __restrict__ xi, T* v, int n0,
+                                                                  const int32_t* __restrict__ level_ptr, int l_begin,
+                                                                  int l_end) {
+    for (int l = l_begin; l < l_end; ++l) {
+        const int64_t s_begin = level_ptr[l] - n0, s_end = level_ptr[l + 1] - n0;
+        for (int64_t sp = s_begin + threadIdx.x; sp < s_end; sp += kRunThreads) {
+            const int64_t base = (sp >> 6) * (int64_t)KP * kTile + (sp & 63);
+            T acc = T(0);
+#pragma unroll
+            for (int m = 0; m < KP; ++m) {
+                const int32_t j = nbr[base + m * kTile];
+                const T w = b[base + m * kTile];
+                const T vj = v[j >= 0 ? j : 0];
+                acc = fma(w, j >= 0 ? vj : T(0), acc);
+            }
+            v[n0 + sp] = fma(sig[sp], xi[n0 + sp], acc);
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T>
+static hipError_t launch_run_t(int kp, const int32_t* nbr, const void* b, const void* sig, const void* xi, void* v,
+                               int n0, const int32_t* level_ptr_dev, int l_begin, int l_end, hipStream_t s) {
+    const T* bp = static_cast<const T*>(b);
+    const T* sp = static_cast<const T*>(sig);
+    const T* ip = static_cast<const T*>(xi);
+    T* op = static_cast<T*>(v);
+    switch (kp) {
+        case 8:
+            hipLaunchKernelGGL((forward_run_kernel<T, 8>), dim3(1), dim3(kRunThreads), 0, s, nbr, bp, sp, ip, op, n0,
+                               level_ptr_dev, l_begin, l_end);
+            break;
+        case 16:
+            hipLaunchKernelGGL((forward_run_kernel<T, 16>), dim3(1), dim3(kRunThreads), 0, s, nbr, bp, sp, ip, op, n0,
+                               level_ptr_dev, l_begin, l_end);
+            break;
+        case 32:
+            hipLaunchKernelGGL((forward_run_kernel<T, 32>), dim3(1), dim3(kRunThreads), 0, s, nbr, bp, sp, ip, op, n0,
+                               level_ptr_dev, l_begin, l_end);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_forward_run(int precision, int kp, const int32_t* nbr, const void* b, const void* sigma,
+                              const void* xi, void* v, int n0, const int32_t* level_ptr_dev, int l_begin, int l_end,
+                              hipStream_t s) {
+    if (precision == VECCHIA_FP32)
+        return launch_run_t<float>(kp, nbr, b, sigma, xi, v, n0, level_ptr_dev, l_begin, l_end, s);
+    return launch_run_t<double>(kp, nbr, b, sigma, xi, v, n0, level_ptr_dev, l_begin, l_end, s);
+}
+
 template <typename T, bool INVERSE>
 static hipError_t launch_apply_t(int kp, const int32_t* nbr, const void* b, const void* sig, const void* in, void* out,
                                  int n0, int64_t s_begin, int64_t s_end, hipStream_t s) {

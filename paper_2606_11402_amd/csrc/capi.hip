@@ -178,13 +178,29 @@ extern "C" int vecchia_forward(const vecchia_view* view, const void* xi, void* v
     });
     if (e != hipSuccess) return hip_fail(e, "vecchia_forward (dense block)");
     const int32_t* lp = view->level_ptr;
-    for (int l = 1; l <= view->n_levels; ++l) {
+    const int L = view->n_levels;
+    for (int l = 1; l <= L;) {
+        // a run of at least two consecutive small batches goes to one workgroup
+        int run_end = l;
+        if (view->level_ptr_dev)
+            while (run_end <= L && lp[run_end + 1] - lp[run_end] <= kRunMaxPoints) ++run_end;
+        if (run_end - l >= 2) {
+            const int l0 = l;
+            e = timed("forward_run", s, [&] {
+                return launch_forward_run(view->precision, view->kp, view->nbr, ws<char>(view, lay.b),
+                                          ws<char>(view, lay.sigma), xi, v, view->n0, view->level_ptr_dev, l0, run_end, s);
+            });
+            if (e != hipSuccess) return hip_fail(e, "vecchia_forward (run of small batches)");
+            l = run_end;
+            continue;
+        }
         const int64_t a = lp[l] - view->n0, b = lp[l + 1] - view->n0;
         e = timed("forward_level", s, [&] {
             return launch_forward_level(view->precision, view->kp, view->nbr, ws<char>(view, lay.b),
                                         ws<char>(view, lay.sigma), xi, v, view->n0, a, b, s);
         });
         if (e != hipSuccess) return hip_fail(e, "vecchia_forward (level)");
+        ++l;
     }
     return VECCHIA_OK;
 }

@@ -44,10 +44,13 @@ struct vecchia_graph {
     std::vector<double> xs;            // slot order, 3 per slot (zero padded)
     std::vector<int32_t> tree_perm;    // slot -> input index
     std::vector<int8_t> sdim;          // slot -> split dimension
-    std::vector<int32_t> nbr;          // (n - n0) x k neighbour slots, row r = slot n0 + r
+    std::vector<int32_t> nbr;          // (n - n0) x k neighbours as in-order ranks, row r = slot n0 + r
+    std::vector<int32_t> seq;          // in-order rank -> slot
+    std::vector<int32_t> rank_of;      // slot -> in-order rank
     std::vector<int32_t> depth;        // slot -> depth
     std::vector<int32_t> order;        // storage -> slot
     std::vector<int32_t> pos;          // slot -> storage
+    std::vector<int32_t> pos_r;        // in-order rank -> storage
     std::vector<int32_t> level_ptr;    // n_levels + 2
     double times[4] = {0, 0, 0, 0};
 };
@@ -238,65 +241,120 @@ inline double sqdist(const double* a, const double* b, int d) {
     return acc;
 }
 
-// The k nearest slots j < i of slot i (Sec. 2.1), written ascending by (D, j).
-void query_preceding(const vecchia_graph& g, int64_t i, int32_t* out) {
+// Query tree in in-order layout: the nodes of every subtree occupy one
+// contiguous range of ranks, so the bottom of a search touches nearby memory.
+struct QNode {
+    double c[3];
+    int32_t slot;
+    int32_t left, right;   // in-order ranks of the children, -1 if absent
+    int32_t sdim;
+};
+
+void inorder(vecchia_graph& g) {
+    const int64_t n = g.n;
+    g.seq.resize(n);
+    g.rank_of.resize(n);
+    std::vector<int64_t> stack;
+    stack.reserve(128);
+    int64_t t = 0, r = 0;
+    while (t < n || !stack.empty()) {
+        while (t < n) {
+            stack.push_back(t);
+            t = left_child(t);
+        }
+        t = stack.back();
+        stack.pop_back();
+        g.seq[r] = (int32_t)t;
+        g.rank_of[t] = (int32_t)r;
+        ++r;
+        t = right_child(t);
+    }
+}
+
+// The k nearest slots j < i of slot i (Sec. 2.1), written ascending by
+// (D, j) as in-order ranks.
+void query_preceding(const vecchia_graph& g, const QNode* nodes, int64_t i, int32_t* out) {
     const double* q = &g.xs[i * 3];
     const int d = g.d;
     Candidates cand;
     cand.cap = (int)std::min<int64_t>(g.k, i);
     struct Item {
-        int64_t node;
+        int32_t rank;
         double bound;
     };
     Item stack[192];
     int sp = 0;
-    stack[sp++] = Item{0, 0.0};
+    stack[sp++] = Item{g.rank_of[0], 0.0};
     while (sp > 0) {
         const Item it = stack[--sp];
         if (cand.full() && it.bound > cand.worst()) continue;
-        const int64_t t = it.node;
-        const double* p = &g.xs[t * 3];
-        cand.offer(sqdist(q, p, d), (int32_t)t);
-        const int s = g.sdim[t];
-        const double diff = q[s] - p[s];
+        const QNode& nd = nodes[it.rank];
+        const int64_t t = nd.slot;
+        cand.offer(sqdist(q, nd.c, d), (int32_t)t);
+        const int s = nd.sdim;
+        const double diff = q[s] - nd.c[s];
         const int64_t l = left_child(t), r = right_child(t);
-        const int64_t near_c = diff < 0.0 ? l : r, far_c = diff < 0.0 ? r : l;
+        const bool left_near = diff < 0.0;
+        const int64_t near_c = left_near ? l : r, far_c = left_near ? r : l;
+        const int32_t near_r = left_near ? nd.left : nd.right, far_r = left_near ? nd.right : nd.left;
         const double plane = std::max(it.bound, diff * diff);
-        if (far_c < i && !(cand.full() && plane > cand.worst())) stack[sp++] = Item{far_c, plane};
-        if (near_c < i) stack[sp++] = Item{near_c, it.bound};
+        if (far_c < i && !(cand.full() && plane > cand.worst())) stack[sp++] = Item{far_r, plane};
+        if (near_c < i) stack[sp++] = Item{near_r, it.bound};
     }
-    // heap -> ascending order
     const int m = cand.size;
     int32_t idx[VECCHIA_KMAX];
     for (int a = 0; a < m; ++a) idx[a] = a;
     std::sort(idx, idx + m, [&](int a, int b) {
         return cand.dist[a] < cand.dist[b] || (cand.dist[a] == cand.dist[b] && cand.slot[a] < cand.slot[b]);
     });
-    for (int a = 0; a < m; ++a) out[a] = cand.slot[idx[a]];
+    for (int a = 0; a < m; ++a) out[a] = g.rank_of[cand.slot[idx[a]]];
     for (int a = m; a < g.k; ++a) out[a] = -1;
 }
 
 void build_neighbours(vecchia_graph& g, int nthreads) {
-    const int64_t ns = g.n - g.n0;
+    const int64_t n = g.n, ns = g.n - g.n0;
+    inorder(g);
+    std::vector<QNode> nodes(n);
+    parallel_for(n, 1 << 16, nthreads, [&](int64_t a, int64_t b) {
+        for (int64_t r = a; r < b; ++r) {
+            const int64_t t = g.seq[r];
+            QNode& nd = nodes[r];
+            for (int c = 0; c < 3; ++c) nd.c[c] = g.xs[t * 3 + c];
+            nd.slot = (int32_t)t;
+            const int64_t l = left_child(t), rr = right_child(t);
+            nd.left = l < n ? g.rank_of[l] : -1;
+            nd.right = rr < n ? g.rank_of[rr] : -1;
+            nd.sdim = g.sdim[t];
+        }
+    });
     g.nbr.resize((size_t)ns * g.k);
-    parallel_for(ns, 2048, nthreads, [&](int64_t a, int64_t b) {
-        for (int64_t r = a; r < b; ++r) query_preceding(g, g.n0 + r, &g.nbr[(size_t)r * g.k]);
+    // queries in in-order sequence: consecutive queries search the same region
+    parallel_for(n, 2048, nthreads, [&](int64_t a, int64_t b) {
+        for (int64_t r = a; r < b; ++r) {
+            const int64_t i = g.seq[r];
+            if (i >= g.n0) query_preceding(g, nodes.data(), i, &g.nbr[(size_t)(i - g.n0) * g.k]);
+        }
     });
 }
 
+// Depths in slot order (the recurrence of Sec. 2.2), kept in rank space so
+// that the depths of a point's neighbours, its spatial neighbours, are read
+// from nearby memory.
 void build_depth(vecchia_graph& g) {
-    g.depth.assign(g.n, 0);
+    std::vector<int32_t> dr(g.n, 0);
     int32_t maxd = 0;
     for (int64_t i = g.n0; i < g.n; ++i) {
         const int32_t* row = &g.nbr[(size_t)(i - g.n0) * g.k];
         int32_t dm = 0;
         for (int m = 0; m < g.k; ++m) {
             if (row[m] < 0) break;
-            dm = std::max(dm, g.depth[row[m]]);
+            dm = std::max(dm, dr[row[m]]);
         }
-        g.depth[i] = dm + 1;
+        dr[g.rank_of[i]] = dm + 1;
         maxd = std::max(maxd, dm + 1);
     }
+    g.depth.resize(g.n);
+    for (int64_t t = 0; t < g.n; ++t) g.depth[t] = dr[g.rank_of[t]];
     g.n_levels = g.n > g.n0 ? maxd : 0;
 }
 
@@ -313,21 +371,14 @@ void build_storage(vecchia_graph& g) {
     g.order.assign(n, -1);
     g.pos.assign(n, -1);
     for (int64_t t = 0; t < g.n0; ++t) g.order[t] = (int32_t)t;
-    // in-order traversal of the tree: spatially coherent sequence of slots
-    std::vector<int64_t> stack;
-    stack.reserve(128);
-    int64_t t = 0;
-    while (t < n || !stack.empty()) {
-        while (t < n) {
-            stack.push_back(t);
-            t = left_child(t);
-        }
-        t = stack.back();
-        stack.pop_back();
+    // inside a batch: in-order sequence of the tree (spatially coherent)
+    for (int64_t r = 0; r < n; ++r) {
+        const int64_t t = g.seq[r];
         if (t >= g.n0) g.order[fill[g.depth[t]]++] = (int32_t)t;
-        t = right_child(t);
     }
     for (int64_t s = 0; s < n; ++s) g.pos[g.order[s]] = (int32_t)s;
+    g.pos_r.resize(n);
+    for (int64_t r = 0; r < n; ++r) g.pos_r[r] = g.pos[g.seq[r]];
 }
 
 }  // namespace
@@ -407,7 +458,7 @@ extern "C" int graph_export_nbr(const vecchia_graph* g, int32_t layout, int32_t*
         for (int64_t sp = 0; sp < ns; ++sp) {
             const int32_t t = g->order[g->n0 + sp];
             const int32_t* row = &g->nbr[(size_t)(t - g->n0) * k];
-            for (int m = 0; m < k; ++m) nbr[sp * k + m] = row[m] >= 0 ? g->pos[row[m]] : -1;
+            for (int m = 0; m < k; ++m) nbr[sp * k + m] = row[m] >= 0 ? g->pos_r[row[m]] : -1;
         }
         return VECCHIA_OK;
     }
@@ -420,7 +471,7 @@ extern "C" int graph_export_nbr(const vecchia_graph* g, int32_t layout, int32_t*
                 if (sp < ns && m < k) {
                     const int32_t t = g->order[g->n0 + sp];
                     const int32_t j = g->nbr[(size_t)(t - g->n0) * k + m];
-                    v = j >= 0 ? g->pos[j] : -1;
+                    v = j >= 0 ? g->pos_r[j] : -1;
                 }
                 nbr[(tile * kp + m) * 64 + lane] = v;
             }
@@ -453,7 +504,7 @@ extern "C" int graph_export_children(const vecchia_graph* g, int64_t* child_ptr,
         const int32_t t = g->order[g->n0 + sp];
         const int32_t* row = &g->nbr[(size_t)(t - g->n0) * g->k];
         for (int m = 0; m < g->k; ++m)
-            if (row[m] >= 0) cnt[g->pos[row[m]] + 1]++;
+            if (row[m] >= 0) cnt[g->pos_r[row[m]] + 1]++;
     }
     for (int64_t j = 0; j < g->n; ++j) cnt[j + 1] += cnt[j];
     std::memcpy(child_ptr, cnt.data(), sizeof(int64_t) * (g->n + 1));
@@ -461,7 +512,7 @@ extern "C" int graph_export_children(const vecchia_graph* g, int64_t* child_ptr,
         const int32_t t = g->order[g->n0 + sp];
         const int32_t* row = &g->nbr[(size_t)(t - g->n0) * g->k];
         for (int m = 0; m < g->k; ++m)
-            if (row[m] >= 0) child[cnt[g->pos[row[m]]]++] = (int32_t)(sp * g->kp + m);
+            if (row[m] >= 0) child[cnt[g->pos_r[row[m]]]++] = (int32_t)(sp * g->kp + m);
     }
     return VECCHIA_OK;
 }

@@ -95,10 +95,12 @@ private:
 enum State { BUILDING = 0, QUEUED = 1, RUNNING = 2, DONE = 3, FAILED = 4, CANCELLED = 5 };
 
 struct Footprint {
-    size_t x = 0, nbr = 0, ws = 0, in = 0, out = 0, ld = 0, total = 0;
+    size_t x = 0, nbr = 0, ws = 0, in = 0, out = 0, ld = 0, lp = 0, total = 0;
 };
 
-Footprint footprint(int64_t n, int kp, int n0) {
+// Device bytes of one request with n_levels batches (n - n0 is an upper bound
+// before the graph is built).
+Footprint footprint(int64_t n, int kp, int n0, int64_t n_levels) {
     Footprint f;
     const int64_t ns = n - n0;
     const int64_t tiles = (ns + 63) / 64;
@@ -115,6 +117,8 @@ Footprint footprint(int64_t n, int kp, int n0) {
     off = vk::align256(off + (size_t)n * sizeof(float));
     f.ld = off;
     off = vk::align256(off + sizeof(double));
+    f.lp = off;
+    off = vk::align256(off + (size_t)(n_levels + 2) * sizeof(int32_t));
     f.total = off;
     return f;
 }
@@ -138,6 +142,7 @@ struct Request {
     float* h_in = nullptr;
     float* h_out = nullptr;
     double* h_ld = nullptr;
+    int32_t* h_lp = nullptr;
     std::vector<float> mock_out;
     // device
     Footprint fp;
@@ -156,6 +161,8 @@ void free_pinned(Request& r) {
     if (r.h_in) (void)hipHostFree(r.h_in);
     if (r.h_out) (void)hipHostFree(r.h_out);
     if (r.h_ld) (void)hipHostFree(r.h_ld);
+    if (r.h_lp) (void)hipHostFree(r.h_lp);
+    r.h_lp = nullptr;
     r.h_x = nullptr;
     r.h_nbr = nullptr;
     r.h_in = r.h_out = nullptr;
@@ -195,6 +202,7 @@ void build_request(vecchia_server* s, Request* r) {
         r->order.resize(r->n);
         r->level_ptr.resize(r->n_levels + 2);
         graph_export(g, r->order.data(), nullptr, r->level_ptr.data(), nullptr);
+        r->fp = footprint(r->n, r->kp, r->n0, r->n_levels);
         const int64_t tiles = std::max<int64_t>((r->n - r->n0 + 63) / 64, 1);
         if (!s->mock) {
             hipError_t e = hipHostMalloc((void**)&r->h_x, (size_t)r->n * 3 * sizeof(float), hipHostMallocDefault);
@@ -202,11 +210,14 @@ void build_request(vecchia_server* s, Request* r) {
             if (e == hipSuccess) e = hipHostMalloc((void**)&r->h_in, (size_t)r->n * sizeof(float), hipHostMallocDefault);
             if (e == hipSuccess) e = hipHostMalloc((void**)&r->h_out, (size_t)r->n * sizeof(float), hipHostMallocDefault);
             if (e == hipSuccess) e = hipHostMalloc((void**)&r->h_ld, sizeof(double), hipHostMallocDefault);
+            if (e == hipSuccess)
+                e = hipHostMalloc((void**)&r->h_lp, (size_t)(r->n_levels + 2) * sizeof(int32_t), hipHostMallocDefault);
             if (e != hipSuccess) {
                 rc = VECCHIA_ENOMEM;
                 r->error = std::string("pinned staging: ") + hipGetErrorString(e);
             } else {
                 std::fill(r->h_nbr, r->h_nbr + (size_t)tiles * r->kp * 64, -1);
+                std::memcpy(r->h_lp, r->level_ptr.data(), (size_t)(r->n_levels + 2) * sizeof(int32_t));
                 graph_export_points(g, VECCHIA_FP32, r->h_x);
                 if (r->n > r->n0) graph_export_nbr(g, 1, r->h_nbr);
                 if (!r->input.empty())
@@ -261,6 +272,8 @@ int launch_request(vecchia_server* s, Request* r) {
         e = hipMemcpyAsync(d + f.nbr, r->h_nbr, (size_t)tiles * r->kp * 64 * sizeof(int32_t), hipMemcpyHostToDevice, st);
     if (e == hipSuccess && r->op != VECCHIA_OP_LOGDET)
         e = hipMemcpyAsync(d + f.in, r->h_in, (size_t)r->n * sizeof(float), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d + f.lp, r->h_lp, (size_t)(r->n_levels + 2) * sizeof(int32_t), hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return vecchia_set_error(VECCHIA_EHIP, "serve upload: %s", hipGetErrorString(e));
     vecchia_view& v = r->view;
     v.n = r->n;
@@ -273,6 +286,7 @@ int launch_request(vecchia_server* s, Request* r) {
     v.x = d + f.x;
     v.nbr = reinterpret_cast<const int32_t*>(d + f.nbr);
     v.level_ptr = r->level_ptr.data();
+    v.level_ptr_dev = reinterpret_cast<const int32_t*>(d + f.lp);
     v.child_ptr = nullptr;
     v.child = nullptr;
     v.workspace = d + f.ws;
@@ -342,7 +356,7 @@ extern "C" int serve_request_bytes(int64_t n, int32_t k, int32_t n0, size_t* byt
     const int kp = vecchia_padded_k(k);
     if (!bytes || kp < 0 || n < 1 || n0 < 1 || n0 > n)
         return vecchia_set_error(VECCHIA_EINVAL, "serve_request_bytes: bad arguments");
-    *bytes = footprint(n, kp, n0).total;
+    *bytes = footprint(n, kp, n0, n - n0).total;
     return VECCHIA_OK;
 }
 
@@ -359,7 +373,7 @@ extern "C" int serve_submit(vecchia_server* s, const double* x, int64_t n, int32
                                  VECCHIA_KMAX, VECCHIA_N0MAX);
     if (kern->kind < 0 || kern->kind > 2 || !(kern->sigma > 0) || !(kern->ell > 0) || !(kern->nugget >= 0))
         return vecchia_set_error(VECCHIA_EINVAL, "serve_submit: bad kernel parameters");
-    const Footprint fp = footprint(n, kp, n0);
+    const Footprint fp = footprint(n, kp, n0, n - n0);   // exact size once the graph is built
     std::unique_ptr<Request> r(new Request());
     r->fp = fp;
     std::lock_guard<std::mutex> lk(s->mu);

@@ -127,6 +127,7 @@ class DeviceGraph:
         self.precision = precision
         self.device = torch.device(device)
         self.level_ptr = np.ascontiguousarray(g.level_ptr, dtype=np.int32)
+        self.level_ptr_dev = torch.from_numpy(self.level_ptr).to(self.device)
         self.x = torch.from_numpy(g.points(precision)).to(self.device)
         nbr = g.nbr(layout=1)
         self.nbr = torch.from_numpy(nbr if nbr.size else np.full(1, -1, np.int32)).to(self.device)
@@ -167,6 +168,7 @@ class Factor:
         v.x = dg.x.data_ptr()
         v.nbr = dg.nbr.data_ptr()
         v.level_ptr = dg.level_ptr.ctypes.data
+        v.level_ptr_dev = dg.level_ptr_dev.data_ptr()
         v.child_ptr = dg.child_ptr.data_ptr() if dg.child_ptr is not None else None
         v.child = dg.child.data_ptr() if dg.child is not None else None
         v.workspace = workspace.data_ptr()
