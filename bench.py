@@ -12,6 +12,8 @@ of width 1e-3, k = 32, squared-exponential kernel ell = 0.02, nugget 1e-6,
 FP32 storage with FP64 pivots and logdet.
 """
 import argparse
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -47,9 +49,70 @@ def factor_flops_per_point(k, kind, refine):
     return total
 
 
+def factor_bytes_per_point(k, esz):
+    # neighbour indices, gathered neighbour coordinates, own coordinates, b and sigma out
+    return 4 * k + 3 * esz * k + 3 * esz + esz * k + esz
+
+
 def apply_bytes_per_point(k, esz):
     # neighbour index + coefficient + gathered v per neighbour, sigma, xi/v in, v/xi out
     return 4 * k + esz * k + esz * k + 3 * esz
+
+
+def kernel_sources(precision_name, kp):
+    """Source files that define the factor kernel of this precision and width."""
+    csrc = os.path.join(ROOT, "paper_2606_11402_amd", "csrc")
+    return [os.path.join(csrc, f) for f in
+            ("common.h", "lanes.h", "factor_kernel.h", "factor_%s_k%d.hip" % (precision_name, kp))]
+
+
+def source_digest(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        h.update(os.path.basename(p).encode())
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel, workload, digest):
+    """HBM bytes per launch of `kernel` on `workload` from a committed counter
+    summary (profiles/traffic_*.txt, lines "key: value"), or None when there is
+    none or it was taken on other kernel sources than the current ones."""
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "traffic_*.txt"))):
+        kv = {}
+        with open(path) as f:
+            for line in f:
+                if ":" in line and not line.startswith((" ", "#")):
+                    a, b = line.split(":", 1)
+                    kv[a.strip()] = b.strip()
+        if kv.get("kernel") != kernel or kv.get("workload") != workload:
+            continue
+        if kv.get("source_digest") != digest:
+            log("traffic summary %s was taken on other kernel sources; traffic = null" % os.path.basename(path))
+            return None
+        try:
+            return {"fetch_bytes": float(kv["fetch_bytes_per_launch"]),
+                    "write_bytes": float(kv["write_bytes_per_launch"]),
+                    "copy_scale_fetch": float(kv["copy_scale_fetch"]),
+                    "copy_scale_write": float(kv["copy_scale_write"]),
+                    "summary": "profiles/" + os.path.basename(path)}
+        except (KeyError, ValueError):
+            return None
+    return None
+
+
+def calibrate_copy():
+    """One plain 1 GiB device-to-device copy (three times), for scaling the
+    FETCH_SIZE / WRITE_SIZE counters: the copy reads and writes 2^30 bytes."""
+    import torch
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": src.numel() * 4, "copies": 3}), flush=True)
 
 
 def main():
@@ -65,12 +128,18 @@ def main():
     ap.add_argument("--no-check", action="store_true", help="skip the sampled oracle check")
     ap.add_argument("--cpu-sample", type=int, default=8192)
     ap.add_argument("--cpu-passes", type=int, default=8)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures the Vecchia hot path on one GPU only; runs on several GPUs are not "
               "part of this build (see DESIGN.md for how the path would shard).", file=sys.stderr)
         sys.exit(2)
+
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
 
     import numpy as np
     import torch
@@ -153,7 +222,8 @@ def main():
     f_ms = prof["factor_sparse"][0] / prof["factor_sparse"][1]
     flops = factor_flops_per_point(k, w.kind, precision == FP32) * ns
     f_tflops = flops / (f_ms * 1e-3) / 1e12
-    fwd_ms = (prof["forward_level"][0] + prof.get("forward_dense", (0.0, 0))[0]) / steps
+    fwd_ms = (prof["forward_level"][0] + prof.get("forward_dense", (0.0, 0))[0]
+              + prof.get("forward_run", (0.0, 0))[0]) / steps
     ld_ms = prof["logdet"][0] / prof["logdet"][1]
     inv_ms = (prof["inverse_sparse"][0] + prof.get("inverse_dense", (0.0, 0))[0]) / steps
     inv_sparse_ms = prof["inverse_sparse"][0] / prof["inverse_sparse"][1]
@@ -162,21 +232,31 @@ def main():
     ldbytes = 8 * ((ns + 63) // 64)
     fl_gbs = (bpp * ns + ldbytes) / ((fwd_ms + ld_ms) * 1e-3) / 1e9
     inv_gbs = bpp * ns / (inv_sparse_ms * 1e-3) / 1e9
-    levels_ms = prof["forward_level"][0] / steps
+    levels_ms = (prof["forward_level"][0] + prof.get("forward_run", (0.0, 0))[0]) / steps
+    kp = 8 if k <= 8 else (16 if k <= 16 else 32)
+    digest = source_digest(kernel_sources("f32" if precision == FP32 else "f64", kp))
+    tr = read_traffic("factor_sparse", w.name if args.n is None and args.k is None else None, digest)
+    traffic, traffic_detail = None, None
+    if tr is not None:
+        traffic = tr["fetch_bytes"] + tr["write_bytes"]
+        traffic_detail = {"fetch_bytes": tr["fetch_bytes"], "write_bytes": tr["write_bytes"],
+                          "copy_scale_fetch": tr["copy_scale_fetch"], "copy_scale_write": tr["copy_scale_write"],
+                          "algorithmic_bytes": factor_bytes_per_point(k, esz) * ns, "summary": tr["summary"]}
 
     roofline = {
         "kernel": "factor_sparse (Eq. 2 per point: gather, K_cc, Cholesky, solves, refinement)",
         "bound": "alu", "achieved": round(f_tflops, 3), "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-        "frac": round(f_tflops / VALU_PEAK_TFLOPS, 4), "traffic": None,
+        "frac": round(f_tflops / VALU_PEAK_TFLOPS, 4), "traffic": traffic,
         "flops_per_point": factor_flops_per_point(k, w.kind, precision == FP32), "points_per_launch": ns,
-        "avg_launch_ms": round(f_ms, 4),
+        "avg_launch_ms": round(f_ms, 4), "source_digest": digest, "traffic_detail": traffic_detail,
     }
     others = {
         "forward": {"bound": "hbm", "achieved": round(fwd_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(fwd_gbs / HBM_PEAK_GBS, 4), "bytes_per_point": bpp,
                     "ms_per_forward": round(fwd_ms, 4), "launches_per_forward": g.n_levels + 1},
         "forward+logdet": {"bound": "hbm", "achieved": round(fl_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": round(fl_gbs / HBM_PEAK_GBS, 4), "ms": round(fwd_ms + ld_ms, 4)},
+                           "frac": round(fl_gbs / HBM_PEAK_GBS, 4), "ms": round(fwd_ms + ld_ms, 4),
+                           "small_batch_runs_ms": round(prof.get("forward_run", (0.0, 0))[0] / steps, 4)},
         "inverse_sparse": {"bound": "hbm", "achieved": round(inv_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": round(inv_gbs / HBM_PEAK_GBS, 4), "avg_launch_ms": round(inv_sparse_ms, 4)},
     }

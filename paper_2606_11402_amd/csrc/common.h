@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstddef>
 #include <cstdint>
 
@@ -60,10 +61,14 @@ inline Layout workspace_layout(int64_t n, int kp, int n0, int precision) {
 }
 
 // Covariance parameters, pre-scaled on the host.  The e_* constants carry a
-// factor log2(e) so that float kernel values use the hardware exp2.
+// factor log2(e) so that float kernel values use the hardware exp2; sigma^2
+// enters the float exponential as its base-2 logarithm (one rounding of the
+// argument instead of a multiply after the exp2).
 template <typename T>
 struct Cov {
     T s2;          // sigma^2
+    T ls2;         // log2(sigma^2)
+    T m32_lin;     // -ln(2) sigma^2: sigma^2 (1 + a) = sigma^2 + m32_lin * (-a log2(e))
     T inv_ell;     // 1/ell
     T c_m32;       // sqrt(3)/ell
     T c_se;        // -1/(2 ell^2)
@@ -77,6 +82,8 @@ inline Cov<T> make_cov(const vecchia_kernel& k) {
     const double log2e = 1.4426950408889634, sqrt3 = 1.7320508075688772;
     Cov<T> c;
     c.s2 = (T)(k.sigma * k.sigma);
+    c.ls2 = (T)std::log2(k.sigma * k.sigma);
+    c.m32_lin = (T)(-0.6931471805599453 * k.sigma * k.sigma);
     c.inv_ell = (T)(1.0 / k.ell);
     c.c_m32 = (T)(sqrt3 / k.ell);
     c.c_se = (T)(-0.5 / (k.ell * k.ell));
@@ -99,12 +106,12 @@ __device__ __forceinline__ double rsqrt_f64(double d) {
 template <int KIND>
 __device__ __forceinline__ float cov_r2(float r2, const Cov<float>& c) {
     if constexpr (KIND == 0) {
-        return c.s2 * __builtin_amdgcn_exp2f(__builtin_amdgcn_sqrtf(r2) * c.e_exp);
+        return __builtin_amdgcn_exp2f(__builtin_fmaf(__builtin_amdgcn_sqrtf(r2), c.e_exp, c.ls2));
     } else if constexpr (KIND == 1) {
         const float t = __builtin_amdgcn_sqrtf(r2) * c.e_m32;            // -a log2(e)
-        return c.s2 * __builtin_fmaf(t, -0.6931471805599453f, 1.0f) * __builtin_amdgcn_exp2f(t);
+        return __builtin_fmaf(t, c.m32_lin, c.s2) * __builtin_amdgcn_exp2f(t);
     } else {
-        return c.s2 * __builtin_amdgcn_exp2f(r2 * c.e_se);
+        return __builtin_amdgcn_exp2f(__builtin_fmaf(r2, c.e_se, c.ls2));
     }
 }
 

@@ -244,17 +244,29 @@ __device__ __forceinline__ void factor_point(const TX* __restrict__ x, const int
             constexpr int p = PI;
             res[p] = (double)kc[p] - nug * (double)bv[p];
         });
+        // K_cc is symmetric: for column l the lane evaluates only its row
+        // blocks p >= block(l).  Each value enters its own row (times b_l)
+        // and, below the diagonal block, also row l (times the lane's b_row),
+        // the latter summed over the group and added by the owner of row l.
+        // Every entry of K_cc b is then counted once, with half the kernel
+        // evaluations of the full product.
         static_for<0, K>([&](auto LI) {
             constexpr int l = LI, pl = l / P, rl = l % P;
             const T y0 = group_bcast<P, rl>(c0[pl]);
             const T y1 = group_bcast<P, rl>(c1[pl]);
             const T y2 = group_bcast<P, rl>(c2[pl]);
             const double bl = (double)group_bcast<P, rl>(bv[pl]);
-            static_for<0, R>([&](auto PI) {
+            double col = 0.0;
+            static_for<pl, R>([&](auto PI) {
                 constexpr int p = PI;
-                const T val = cov_r2<KIND>(sqdist3(c0[p], c1[p], c2[p], y0, y1, y2), cov);
-                res[p] = fma(-(double)val, bl, res[p]);
+                const double val = (double)cov_r2<KIND>(sqdist3(c0[p], c1[p], c2[p], y0, y1, y2), cov);
+                res[p] = fma(-val, bl, res[p]);
+                if constexpr (p > pl) col = fma(-val, (double)bv[p], col);
             });
+            if constexpr (pl + 1 < R) {
+                col = group_sum<P>(col);
+                res[pl] += (r == rl) ? col : 0.0;
+            }
         });
         T dz[R];
         static_for<0, R>([&](auto PI) { dz[(int)PI] = (T)res[(int)PI]; });
