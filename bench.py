@@ -222,8 +222,7 @@ def main():
     f_ms = prof["factor_sparse"][0] / prof["factor_sparse"][1]
     flops = factor_flops_per_point(k, w.kind, precision == FP32) * ns
     f_tflops = flops / (f_ms * 1e-3) / 1e12
-    fwd_ms = (prof["forward_level"][0] + prof.get("forward_dense", (0.0, 0))[0]
-              + prof.get("forward_run", (0.0, 0))[0]) / steps
+    fwd_ms = sum(t for name, (t, _) in prof.items() if name.startswith("forward_")) / steps
     ld_ms = prof["logdet"][0] / prof["logdet"][1]
     inv_ms = (prof["inverse_sparse"][0] + prof.get("inverse_dense", (0.0, 0))[0]) / steps
     inv_sparse_ms = prof["inverse_sparse"][0] / prof["inverse_sparse"][1]
@@ -232,7 +231,8 @@ def main():
     ldbytes = 8 * ((ns + 63) // 64)
     fl_gbs = (bpp * ns + ldbytes) / ((fwd_ms + ld_ms) * 1e-3) / 1e9
     inv_gbs = bpp * ns / (inv_sparse_ms * 1e-3) / 1e9
-    levels_ms = (prof["forward_level"][0] + prof.get("forward_run", (0.0, 0))[0]) / steps
+    levels_ms = sum(t for name, (t, _) in prof.items()
+                    if name.startswith("forward_") and name != "forward_dense") / steps
     kp = 8 if k <= 8 else (16 if k <= 16 else 32)
     digest = source_digest(kernel_sources("f32" if precision == FP32 else "f64", kp))
     tr = read_traffic("factor_sparse", w.name if args.n is None and args.k is None else None, digest)
@@ -253,10 +253,13 @@ def main():
     others = {
         "forward": {"bound": "hbm", "achieved": round(fwd_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(fwd_gbs / HBM_PEAK_GBS, 4), "bytes_per_point": bpp,
-                    "ms_per_forward": round(fwd_ms, 4), "launches_per_forward": g.n_levels + 1},
+                    "ms_per_forward": round(fwd_ms, 4), "launches_per_forward": sum(c for name, (_, c) in prof.items()
+                                                                if name.startswith("forward_")) // steps},
         "forward+logdet": {"bound": "hbm", "achieved": round(fl_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": round(fl_gbs / HBM_PEAK_GBS, 4), "ms": round(fwd_ms + ld_ms, 4),
-                           "small_batch_runs_ms": round(prof.get("forward_run", (0.0, 0))[0] / steps, 4)},
+                           "small_batch_runs_ms": round(prof.get("forward_run", (0.0, 0))[0] / steps, 4),
+                           "dataflow_ms": round(prof.get("forward_flow", (0.0, 0))[0] / steps, 4),
+                           "per_batch_launches_ms": round(prof.get("forward_level", (0.0, 0))[0] / steps, 4)},
         "inverse_sparse": {"bound": "hbm", "achieved": round(inv_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": round(inv_gbs / HBM_PEAK_GBS, 4), "avg_launch_ms": round(inv_sparse_ms, 4)},
     }

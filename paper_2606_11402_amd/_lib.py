@@ -38,7 +38,7 @@ class ServeStats(ctypes.Structure):
     _fields_ = [("arena_bytes", c_size_t), ("bytes_in_use", c_size_t), ("peak_bytes", c_size_t),
                 ("largest_free", c_size_t), ("building", c_int64), ("queued", c_int64), ("running", c_int64),
                 ("admitted", c_int64), ("completed", c_int64), ("failed", c_int64), ("rejected", c_int64),
-                ("cancelled", c_int64)]
+                ("cancelled", c_int64), ("peak_running", c_int64)]
 
 
 class ViewStruct(ctypes.Structure):

@@ -56,7 +56,7 @@ struct AdjArgs {
     const TS* v;
     const TS* vbar;         // may be null
     const TS* xibar_in;     // may be null
-    TS* w;                  // scratch, N
+    double* w;              // scratch, N: the reverse sweep, double in both precisions
     TS* xibar;              // output (forward part)
     TS* vbar_out;           // output (inverse part)
     double* t0;             // scratch, n0: L0^-T xibar0
@@ -82,9 +82,9 @@ __global__ __launch_bounds__(kBlock) void adj_sweep_kernel(AdjArgs<TS> a, int64_
         const int32_t packed = a.child[e];
         const int64_t sp = packed >> SH;
         const int m = packed & (KP - 1);
-        acc = fma((double)a.b[((sp >> 6) * KP + m) * kTile + (sp & 63)], (double)a.w[a.n0 + sp], acc);
+        acc = fma((double)a.b[((sp >> 6) * KP + m) * kTile + (sp & 63)], a.w[a.n0 + sp], acc);
     }
-    a.w[j] = (TS)acc;
+    a.w[j] = acc;
     if (j >= a.n0) a.xibar[j] = (TS)((double)a.sigma[j - a.n0] * acc);
 }
 
@@ -161,7 +161,7 @@ __global__ __launch_bounds__(kBlock) void adj_theta_kernel(AdjArgs<TS> a) {
     const int64_t s = a.n0 + sp;
 
     const double sig = (double)a.sigma[sp];
-    double omega = a.vbar ? (double)a.w[s] : 0.0;
+    double omega = a.vbar ? a.w[s] : 0.0;
     if (a.xibar_in) omega -= (double)a.xibar_in[s] / sig;
     const double sigma_bar = omega * (double)a.xi[s] + 2.0 * a.ldbar / sig;
     const double sbar = sigma_bar / (2.0 * sig);
@@ -248,7 +248,7 @@ __global__ __launch_bounds__(VECCHIA_N0MAX) void adj_dense_kernel(AdjArgs<TS> a)
     const int n0 = a.n0;
     const double* L = a.l0;
     if (i < n0) {
-        double g = a.vbar ? (double)a.w[i] : 0.0;
+        double g = a.vbar ? a.w[i] : 0.0;
         if (a.xibar_in) g -= a.t0[i];
         G[i] = g;
         Z[i] = (double)a.xi[i];
@@ -258,7 +258,7 @@ __global__ __launch_bounds__(VECCHIA_N0MAX) void adj_dense_kernel(AdjArgs<TS> a)
         double h = 0.0, xb = 0.0;
         for (int m = i; m < n0; ++m) {
             h = fma(L[m * n0 + i], G[m], h);
-            if (a.vbar) xb = fma(L[m * n0 + i], (double)a.w[m], xb);
+            if (a.vbar) xb = fma(L[m * n0 + i], a.w[m], xb);
         }
         H[i] = h;
         if (a.vbar) a.xibar[i] = (TS)xb;
@@ -349,7 +349,7 @@ static hipError_t backward_t(const BackwardLaunch& p, hipStream_t s) {
     a.v = static_cast<const TS*>(p.v);
     a.vbar = static_cast<const TS*>(p.vbar);
     a.xibar_in = static_cast<const TS*>(p.xibar_in);
-    a.w = static_cast<TS*>(p.w);
+    a.w = static_cast<double*>(p.w);
     a.xibar = static_cast<TS*>(p.xibar);
     a.vbar_out = static_cast<TS*>(p.vbar_out);
     a.t0 = p.t0;

@@ -23,11 +23,16 @@ __host__ __device__ constexpr int factor_lanes(int precision, int kp) {
     return precision == VECCHIA_FP32 ? (kp <= 8 ? 1 : 4) : (kp <= 8 ? 1 : (kp <= 16 ? 4 : 8));
 }
 
+// Batch-completion counters of the dataflow forward: [0] chunk ticket,
+// [1 + m] chunks finished of the m-th batch of a launch.
+constexpr int kFlowMaxLevels = 8192;
+constexpr int kFlowWords = 1 + kFlowMaxLevels;
+
 // Device workspace holding one factor.  Offsets are 256-byte aligned.
 struct Layout {
     int64_t ns = 0, ntiles = 0, nparts = 0;
     size_t esz = 0;
-    size_t b = 0, sigma = 0, l0 = 0, ldpart = 0, ld0 = 0, ldstage = 0, status = 0, redo = 0, total = 0;
+    size_t b = 0, sigma = 0, l0 = 0, ldpart = 0, ld0 = 0, ldstage = 0, status = 0, flow = 0, redo = 0, total = 0;
 };
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -53,7 +58,9 @@ inline Layout workspace_layout(int64_t n, int kp, int n0, int precision) {
     w.ldstage = off;
     off = align256(off + 2 * 256 * sizeof(double));
     w.status = off;
-    off = align256(off + 4 * sizeof(uint64_t));
+    off = align256(off + 5 * sizeof(uint64_t));
+    w.flow = off;
+    off = align256(off + kFlowWords * sizeof(uint32_t));
     w.redo = off;
     if (precision == VECCHIA_FP32) off = align256(off + (size_t)(w.ns > 0 ? w.ns : 1) * sizeof(uint32_t));
     w.total = off;
@@ -162,6 +169,13 @@ constexpr int64_t kRunMaxPoints = 2048;  // a batch this small joins a run
 hipError_t launch_forward_run(int precision, int kp, const int32_t* nbr, const void* b, const void* sigma,
                               const void* xi, void* v, int n0, const int32_t* level_ptr_dev, int l_begin, int l_end,
                               hipStream_t stream);
+// Dataflow forward over the batches [l_begin, l_end) in one launch (see
+// forward_flow_kernel); `flow` holds kFlowWords counters, reset here; a wait
+// that reaches its limit sets *flag (status word 4 of the workspace).
+constexpr int kFlowChunk = 256;          // points per chunk (one workgroup)
+hipError_t launch_forward_flow(int precision, int kp, const int32_t* nbr, const void* b, const void* sigma,
+                               const void* xi, void* v, int n0, const int32_t* level_ptr_dev, int l_begin, int l_end,
+                               int64_t s_begin, int64_t s_end, uint32_t* flow, uint64_t* flag, hipStream_t stream);
 hipError_t launch_inverse_dense(int precision, const double* l0, int n0, const void* v, void* xi, hipStream_t stream);
 hipError_t launch_inverse_sparse(int precision, int kp, const int32_t* nbr, const void* b, const void* sigma,
                                  const void* v, void* xi, int n0, int64_t ns, hipStream_t stream);
@@ -181,20 +195,21 @@ struct BackwardLaunch {
 };
 hipError_t launch_backward(const BackwardLaunch& p, hipStream_t stream);
 
-// Scratch of vecchia_backward: w (N values), t0 (n0 doubles), theta partials
+// Scratch of vecchia_backward: w (N doubles), t0 (n0 doubles), theta partials
 // (2 doubles per block of the theta kernel), dense theta (2 doubles).
 struct BackwardScratch {
     size_t w = 0, t0 = 0, part = 0, dense = 0, total = 0;
     int64_t nblocks = 0;
 };
 inline BackwardScratch backward_scratch(int64_t n, int kp, int n0, int precision) {
+    (void)precision;   // the sweep keeps w in double for both storage precisions
     BackwardScratch b;
     const int64_t ns = n - n0;
     const int pts = kBlock / factor_lanes(VECCHIA_FP64, kp);
     b.nblocks = (ns + pts - 1) / pts;
     size_t off = 0;
     b.w = off;
-    off = align256(off + (size_t)n * (precision == VECCHIA_FP64 ? 8 : 4));
+    off = align256(off + (size_t)n * sizeof(double));
     b.t0 = off;
     off = align256(off + (size_t)n0 * sizeof(double));
     b.part = off;

@@ -23,6 +23,7 @@ __global__ __launch_bounds__(kDenseThreads) void factor_dense_kernel(const TX* _
         status[1] = 0;             // failing points
         status[2] = 0;             // FP32 path: points recomputed in double
         status[3] = 0;             // their sum of log sigma, fixed point
+        status[4] = 0;             // a dataflow forward wait reached its limit
     }
     if (i < n0) {
         const double a0 = (double)x[i * 3 + 0], a1 = (double)x[i * 3 + 1], a2 = (double)x[i * 3 + 2];

@@ -190,6 +190,7 @@ struct vecchia_server {
     bool stop = false;
     int64_t next_id = 1;
     int64_t n_admitted = 0, n_done = 0, n_failed = 0, n_rejected = 0, n_cancelled = 0;
+    int64_t peak_running = 0;   // most requests on the device at once
 };
 
 namespace {
@@ -458,6 +459,7 @@ extern "C" int serve_progress(vecchia_server* s, int32_t* n_completed) {
             }
         }
         s->running.push_back(r);
+        s->peak_running = std::max<int64_t>(s->peak_running, (int64_t)s->running.size());
     }
     if (n_completed) *n_completed = (int32_t)s->completed.size();
     return first_error;
@@ -556,6 +558,7 @@ extern "C" int serve_stats(vecchia_server* s, vecchia_serve_stats* out) {
     out->failed = s->n_failed;
     out->rejected = s->n_rejected;
     out->cancelled = s->n_cancelled;
+    out->peak_running = s->peak_running;
     return VECCHIA_OK;
 }
 

@@ -198,11 +198,17 @@ class Factor:
             return torch.empty(self.dg.n, dtype=self.dg.dtype, device=self.dg.device)
         return self._vec(out, "out")
 
-    def forward(self, xi, out=None):
-        """v = F(xi), both in storage order."""
+    def forward(self, xi, out=None, per_batch=False):
+        """v = F(xi), both in storage order.  per_batch=True passes the view
+        without the device copy of level_ptr, so the library launches one
+        kernel per batch instead of its dataflow and small-batch kernels."""
         xi = self._vec(xi, "xi")
         v = self._out(out)
-        _lib.check(self._lib.vecchia_forward(ctypes.byref(self.view), ctypes.c_void_p(xi.data_ptr()),
+        view = self.view
+        if per_batch:
+            view = _lib.ViewStruct.from_buffer_copy(self.view)
+            view.level_ptr_dev = None
+        _lib.check(self._lib.vecchia_forward(ctypes.byref(view), ctypes.c_void_p(xi.data_ptr()),
                                              ctypes.c_void_p(v.data_ptr()), _stream(self.dg.device)),
                    "vecchia_forward")
         return v

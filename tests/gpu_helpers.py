@@ -14,6 +14,33 @@ def rel_err(a, ref):
     return float(np.max(np.abs(a - ref)) / den) if ref.size else 0.0
 
 
+def b_backward_error(og, kern, b, chunk=2048):
+    """Largest normwise backward error of the coefficient rows b (slot order,
+    (Ns, k)) as solutions of K_cc b = k_ci, with K_cc and k_ci evaluated in
+    FP64 by the oracle: max_i |K b - k|_inf / (|K|_inf |b|_inf + |k|_inf).
+    A backward-stable solve gives a few units of roundoff whatever cond(K_cc)
+    is, while the forward error of b grows with cond(K_cc)."""
+    from oracle.covariance import kappa
+    xs, n0 = og.xs, og.n0
+    ns, k = og.nbr.shape
+    worst = 0.0
+    for c0 in range(0, ns, chunk):
+        rows = og.nbr[c0:c0 + chunk]
+        ok = rows >= 0
+        xc = xs[np.maximum(rows, 0)]                                  # (m, k, d)
+        xt = xs[n0 + c0:n0 + c0 + len(rows)]                          # (m, d)
+        r = np.sqrt(np.sum((xc[:, :, None, :] - xc[:, None, :, :]) ** 2, axis=-1))
+        K = kappa(r, kern) + kern.nugget * np.eye(k)
+        mask = ok[:, :, None] & ok[:, None, :]
+        K = np.where(mask, K, np.eye(k))
+        kc = np.where(ok, kappa(np.sqrt(np.sum((xc - xt[:, None, :]) ** 2, axis=-1)), kern), 0.0)
+        bb = np.where(ok, np.asarray(b[c0:c0 + len(rows)], dtype=np.float64), 0.0)
+        res = np.einsum("mij,mj->mi", K, bb) - kc
+        den = np.abs(K).sum(axis=2).max(axis=1) * np.abs(bb).max(axis=1) + np.abs(kc).max(axis=1)
+        worst = max(worst, float(np.max(np.abs(res).max(axis=1) / den)))
+    return worst
+
+
 class Run:
     """Build the graph, upload, factor, forward(xi), inverse(v) on the GPU."""
 

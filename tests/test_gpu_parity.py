@@ -1,7 +1,11 @@
 """HIP path (through the C ABI) against the FP64 oracle.
 
 Tolerances: FP64 path 1e-10 relative, FP32 path 1e-4 relative; vectors use
-max|a - ref| / max|ref|, scalars |a - ref| / |ref|.  The graph itself is
+max|a - ref| / max|ref|, scalars |a - ref| / |ref|.  The coefficients b are
+also judged by their backward error as solutions of K_cc b = k_ci (FP64 K_cc
+from the oracle), which a correct solve keeps at roundoff level however
+ill-conditioned K_cc is; their forward error is bounded by cond(K_cc) times
+that and is stated.  The graph itself is
 compared bit for bit in test_graph_native.py; here it only has to be the
 same graph on both sides (the oracle rebuilds it from the same points)."""
 import math
@@ -14,11 +18,14 @@ import oracle
 import workloads
 from oracle import Kernel, EXP, M32, SE
 from paper_2606_11402_amd import FP32, FP64, VecchiaError
-from gpu_helpers import Run, oracle_run, rel_err
+from gpu_helpers import Run, b_backward_error, oracle_run, rel_err
 
 pytestmark = pytest.mark.gpu
 
 TOL = {FP64: 1e-10, FP32: 1e-4}
+# backward error of b: FP64 solves sit at ~k u64; the FP32 path solves with
+# kernel values rounded to float (relative 6e-8 each) and refines once
+TOL_B_BACKWARD = {FP64: 1e-12, FP32: 1e-5}
 
 
 # Metrics that float storage or the conditioning of K_cc cannot bring under the
@@ -49,10 +56,12 @@ def check_against_oracle(x, k, n0, kern, precision, xi_in, tol=None, report=None
     v_ref_storage = torch.from_numpy(v_in[run.g.slot]).to(run.dtype).cuda()
     xi_inv = run.fac.inverse(v_ref_storage).cpu().numpy()
     errs["xi_inverse"] = rel_err(run.slot_order(xi_inv), oracle.inverse(ref["graph"], fac, v_in))
+    errs["b_backward"] = b_backward_error(ref["graph"], kern, b)
     if report is not None:
         report.update(errs)
     print("errors", precision, errs, flush=True)
     run.fac.status()
+    assert errs["b_backward"] <= TOL_B_BACKWARD[precision], ("b_backward", errs["b_backward"])
     missed = []
     for name in ("sigma", "v", "logdet", "xi_inverse", "xi_roundtrip") + (("b",) if precision == FP64 else ()):
         if errs[name] > tol:
@@ -114,7 +123,11 @@ def test_c2_shape_radial_m32(precision):
     w = workloads.WORKLOADS[2]
     n = 1 << 14
     x = w.points(n)
-    limited = ("xi_inverse",) if precision == FP64 else ("xi_inverse", "sigma", "v", "b")
+    # the radial core (radius 1e-3 against ell = 0.05) gives cond(K_cc) up to
+    # ~1e9: in FP64 the forward error of b reaches ~1e-7 while its backward
+    # error, sigma, v and logdet stay at ~1e-12; in FP32 the float storage of
+    # v limits the round trip through sum |b_m v_m| / sigma_i
+    limited = ("xi_inverse", "b") if precision == FP64 else ("xi_inverse", "sigma", "v", "b", "xi_roundtrip")
     check_against_oracle(x, w.k, 128, Kernel(M32, 1.0, 0.05), precision, w.xi(n), limited=limited)
 
 

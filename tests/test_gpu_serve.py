@@ -1,6 +1,8 @@
 """Serving engine on the GPU: results are identical alone and in a mix of
 concurrent requests, agree with the direct calls and with the oracle, and
 the engine overlaps requests within its HBM budget."""
+import time
+
 import numpy as np
 import pytest
 import torch
@@ -43,6 +45,12 @@ def test_alone_and_in_the_mix_are_identical():
         srv.close()
     srv = Server(budget, n_streams=4, graph_workers=8)
     ids = [submit(srv, r) for r in reqs]
+    # let every graph build finish before the first admission, so that the
+    # first progress call admits as many requests as the budget holds
+    for _ in range(6000):
+        if srv.stats()["queued"] == len(reqs):
+            break
+        time.sleep(0.01)
     res = srv.drain()
     st = srv.stats()
     srv.close()
@@ -52,8 +60,7 @@ def test_alone_and_in_the_mix_are_identical():
             assert got == ref
         else:
             assert np.array_equal(got, ref)
-    single_max = max(Server.request_bytes(len(r[0]), r[1]) for r in reqs)
-    assert st["peak_bytes"] > single_max          # several requests were resident at once
+    assert st["peak_running"] >= 2                # several requests were on the device at once
     assert st["peak_bytes"] <= budget and st["failed"] == 0
 
 

@@ -61,6 +61,7 @@ def test_budget_forces_queueing_and_fifo_completion():
     assert order == ids          # admission is FIFO over graph-ready requests; equal mock latency
     st = srv.stats()
     assert st["bytes_in_use"] == 0 and st["completed"] == 6 and st["peak_bytes"] <= 2 * one + 512
+    assert st["peak_running"] == 2          # the budget holds two requests at a time
     srv.close()
 
 
