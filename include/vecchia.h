@@ -173,11 +173,9 @@ int vecchia_factor(vecchia_view* view, const vecchia_kernel* kern, void* stream)
 /* Alg. 1: v[0:n0] = L0 xi[0:n0], then for every batch l = 1..L in order,
  * v_i = b_i . v[c(i)] + sigma_i xi_i.  xi and v are device arrays of N
  * elements (double or float per view->precision) in storage order; they must
- * not overlap.  With view->level_ptr_dev set, consecutive batches run in one
- * dataflow launch whose batch-completion counters live in the workspace:
- * forwards on one workspace must therefore not overlap in time (one stream,
- * or synchronised streams).  A dataflow wait is bounded; if one reaches its
- * limit the result is invalid and vecchia_status() reports VECCHIA_EHIP. */
+ * not overlap.  One launch per batch; with view->level_ptr_dev set, runs of
+ * consecutive small batches (<= 2048 points) go to one workgroup each, with a
+ * workgroup barrier between batches. */
 int vecchia_forward(const vecchia_view* view, const void* xi, void* v, void* stream);
 
 /* Inverse application xi = F^-1(v): xi[0:n0] = L0^-1 v[0:n0] and
@@ -208,12 +206,10 @@ int vecchia_backward(const vecchia_view* view, const vecchia_kernel* kern,
  * VECCHIA_FP32, how many were recomputed in double (recomputed). */
 int vecchia_factor_counts(const vecchia_view* view, void* stream, int64_t* not_pd, int64_t* recomputed);
 
-/* Synchronises `stream`, then reads the workspace status words.  Returns
- * VECCHIA_OK; VECCHIA_EHIP if a dataflow forward since the last
- * vecchia_factor() had a wait reach its limit (its result is invalid); or
- * VECCHIA_ENOTPD with *first_bad_slot = the smallest storage position whose
- * pivot or conditional variance was not positive (-1 if none; the dense
- * block reports its first bad pivot row). */
+/* Synchronises `stream`, then reads the workspace status word.  Returns
+ * VECCHIA_OK, or VECCHIA_ENOTPD with *first_bad_slot = the smallest storage
+ * position whose pivot or conditional variance was not positive (-1 if
+ * none; the dense block reports its first bad pivot row). */
 int vecchia_status(const vecchia_view* view, void* stream, int64_t* first_bad_slot);
 
 /* ---- serving: continuous batching of requests on one GPU ----------------- */

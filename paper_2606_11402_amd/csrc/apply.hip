@@ -78,159 +78,6 @@ __global__ __launch_bounds__(kRunThreads) void forward_run_kernel(const int32_t*
     }
 }
 
-// Dataflow forward over the batches [l_begin, l_end) in one launch.
-//
-// Workgroups claim chunks of kFlowChunk consecutive sparse positions from a
-// ticket counter, so chunk c is claimed only after chunks 0..c-1 have been
-// claimed by workgroups that are running.  A chunk first loads its neighbour
-// indices, coefficients, sigma and xi (none depends on v); then, for each
-// batch it overlaps, in order, it waits until every chunk overlapping the
-// previous batch has counted itself finished, gathers v, writes its outputs
-// and counts itself finished for that batch.  A wait only ever names chunks
-// with an index <= c, so the earliest unfinished chunk never waits and the
-// launch always drains; the wait is bounded as well (*flag records a wait
-// that hit the limit).  Writes become visible to other workgroups (and to the
-// separate L2 of every XCD) through agent-scope release fences before a
-// batch counter is incremented and acquire fences after a wait.  Compared to
-// one launch per batch, the streaming loads of the next batches overlap the
-// gathers of the current one and there are no launch gaps.
-template <typename T, int KP>
-__global__ __launch_bounds__(kBlock) void forward_flow_kernel(const int32_t* __restrict__ nbr, const T* __restrict__ b,
-                                                              const T* __restrict__ sig, const T* __restrict__ xi,
-                                                              T* v, int n0, const int32_t* __restrict__ level_ptr,
-                                                              int l_begin, int l_end, int64_t s_begin, int64_t s_end,
-                                                              uint32_t* flow, unsigned long long* flag,
-                                                              uint32_t spin_limit) {
-    static_assert(kBlock == kFlowChunk, "one workgroup per chunk");
-    __shared__ int64_t sh_c0;
-    __shared__ int sh_level;
-    if (threadIdx.x == 0) {
-        const int64_t c0 = s_begin + (int64_t)atomicAdd(&flow[0], 1u) * kFlowChunk;
-        // batch holding the chunk's first position: the largest l with level_ptr[l] - n0 <= c0
-        int lo = l_begin, hi = l_end - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if ((int64_t)level_ptr[mid] - n0 <= c0)
-                lo = mid;
-            else
-                hi = mid - 1;
-        }
-        sh_c0 = c0;
-        sh_level = lo;
-    }
-    __syncthreads();
-    const int64_t c0 = sh_c0;
-    const int64_t c1 = c0 + kFlowChunk < s_end ? c0 + kFlowChunk : s_end;
-    const int64_t sp = c0 + threadIdx.x;
-    const bool live = sp < c1;
-    const int64_t spl = live ? sp : c1 - 1;   // lanes past the end read the last point and write nothing
-    const int64_t base = (spl >> 6) * (int64_t)KP * kTile + (spl & 63);
-    int32_t idx[KP];
-    T w[KP];
-#pragma unroll
-    for (int m = 0; m < KP; ++m) {
-        idx[m] = __builtin_nontemporal_load(nbr + base + m * kTile);
-        w[m] = __builtin_nontemporal_load(b + base + m * kTile);
-    }
-    const T sg = sig[spl];
-    const T x = xi[n0 + spl];
-
-    for (int l = sh_level; l < l_end; ++l) {
-        const int64_t a = (int64_t)level_ptr[l] - n0, e = (int64_t)level_ptr[l + 1] - n0;
-        if (a >= c1) break;
-        if (l > l_begin) {
-            const int64_t pa = (int64_t)level_ptr[l - 1] - n0;   // previous batch: [pa, a)
-            if (pa >= c0) {
-                __syncthreads();   // previous batch lies in this chunk: written by this workgroup
-            } else {
-                const uint32_t need =
-                    (uint32_t)((a - 1 - s_begin) / kFlowChunk - (pa - s_begin) / kFlowChunk + 1);
-                if (threadIdx.x == 0) {
-                    uint32_t it = 0;
-                    while (__hip_atomic_load(&flow[1 + (l - 1 - l_begin)], __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT) < need) {
-                        __builtin_amdgcn_s_sleep(2);
-                        if (++it >= spin_limit) {
-                            atomicOr(flag, 1ull);
-                            break;
-                        }
-                    }
-                }
-                __syncthreads();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            }
-        }
-        if (live && sp >= a && sp < e) {
-            T acc = T(0);
-#pragma unroll
-            for (int m = 0; m < KP; ++m) {
-                const int32_t j = idx[m];
-                const T vj = v[j >= 0 ? j : 0];
-                acc = fma(w[m], j >= 0 ? vj : T(0), acc);
-            }
-            v[n0 + sp] = fma(sg, x, acc);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __syncthreads();
-        if (threadIdx.x == 0)
-            __hip_atomic_fetch_add(&flow[1 + (l - l_begin)], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    }
-}
-
-// Zeroes the first `words` counters of a dataflow launch (a kernel, not a
-// memset, so that the forward can be captured in a graph).
-__global__ __launch_bounds__(1024) void flow_reset_kernel(uint32_t* flow, int words) {
-    for (int i = threadIdx.x; i < words; i += blockDim.x) flow[i] = 0u;
-}
-
-// Wait limit of the dataflow forward: about 2^22 sleeps of 128 cycles
-// (~0.2 s), far beyond any batch.
-constexpr uint32_t kFlowSpinLimit = 1u << 22;
-
-template <typename T>
-static hipError_t launch_flow_t(int kp, const int32_t* nbr, const void* b, const void* sig, const void* xi, void* v,
-                                int n0, const int32_t* level_ptr_dev, int l_begin, int l_end, int64_t s_begin,
-                                int64_t s_end, uint32_t* flow, uint64_t* flag, hipStream_t s) {
-    if (s_end <= s_begin) return hipSuccess;
-    if (l_end - l_begin > kFlowMaxLevels) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(flow_reset_kernel, dim3(1), dim3(1024), 0, s, flow, 1 + (l_end - l_begin));
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const unsigned chunks = (unsigned)((s_end - s_begin + kFlowChunk - 1) / kFlowChunk);
-    const T* bp = static_cast<const T*>(b);
-    const T* sp = static_cast<const T*>(sig);
-    const T* ip = static_cast<const T*>(xi);
-    T* op = static_cast<T*>(v);
-    unsigned long long* fl = reinterpret_cast<unsigned long long*>(flag);
-    switch (kp) {
-        case 8:
-            hipLaunchKernelGGL((forward_flow_kernel<T, 8>), dim3(chunks), dim3(kFlowChunk), 0, s, nbr, bp, sp, ip, op,
-                               n0, level_ptr_dev, l_begin, l_end, s_begin, s_end, flow, fl, kFlowSpinLimit);
-            break;
-        case 16:
-            hipLaunchKernelGGL((forward_flow_kernel<T, 16>), dim3(chunks), dim3(kFlowChunk), 0, s, nbr, bp, sp, ip, op,
-                               n0, level_ptr_dev, l_begin, l_end, s_begin, s_end, flow, fl, kFlowSpinLimit);
-            break;
-        case 32:
-            hipLaunchKernelGGL((forward_flow_kernel<T, 32>), dim3(chunks), dim3(kFlowChunk), 0, s, nbr, bp, sp, ip, op,
-                               n0, level_ptr_dev, l_begin, l_end, s_begin, s_end, flow, fl, kFlowSpinLimit);
-            break;
-        default:
-            return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_forward_flow(int precision, int kp, const int32_t* nbr, const void* b, const void* sigma,
-                               const void* xi, void* v, int n0, const int32_t* level_ptr_dev, int l_begin, int l_end,
-                               int64_t s_begin, int64_t s_end, uint32_t* flow, uint64_t* flag, hipStream_t s) {
-    if (precision == VECCHIA_FP32)
-        return launch_flow_t<float>(kp, nbr, b, sigma, xi, v, n0, level_ptr_dev, l_begin, l_end, s_begin, s_end, flow,
-                                    flag, s);
-    return launch_flow_t<double>(kp, nbr, b, sigma, xi, v, n0, level_ptr_dev, l_begin, l_end, s_begin, s_end, flow,
-                                 flag, s);
-}
-
 template <typename T>
 static hipError_t launch_run_t(int kp, const int32_t* nbr, const void* b, const void* sig, const void* xi, void* v,
                                int n0, const int32_t* level_ptr_dev, int l_begin, int l_end, hipStream_t s) {

@@ -194,26 +194,6 @@ extern "C" int vecchia_forward(const vecchia_view* view, const void* xi, void* v
             l = run_end;
             continue;
         }
-        // otherwise the non-empty batches up to the next run of small ones
-        // go to one dataflow launch
-        int flow_end = l;
-        if (view->level_ptr_dev)
-            while (flow_end <= L && flow_end - l < kFlowMaxLevels && lp[flow_end + 1] > lp[flow_end] &&
-                   !(flow_end + 1 <= L && lp[flow_end + 1] - lp[flow_end] <= kRunMaxPoints &&
-                     lp[flow_end + 2] - lp[flow_end + 1] <= kRunMaxPoints))
-                ++flow_end;
-        if (flow_end - l >= 2) {
-            const int l0 = l;
-            e = timed("forward_flow", s, [&] {
-                return launch_forward_flow(view->precision, view->kp, view->nbr, ws<char>(view, lay.b),
-                                           ws<char>(view, lay.sigma), xi, v, view->n0, view->level_ptr_dev, l0,
-                                           flow_end, lp[l0] - view->n0, lp[flow_end] - view->n0,
-                                           ws<uint32_t>(view, lay.flow), ws<uint64_t>(view, lay.status) + 4, s);
-            });
-            if (e != hipSuccess) return hip_fail(e, "vecchia_forward (dataflow batches)");
-            l = flow_end;
-            continue;
-        }
         const int64_t a = lp[l] - view->n0, b = lp[l + 1] - view->n0;
         e = timed("forward_level", s, [&] {
             return launch_forward_level(view->precision, view->kp, view->nbr, ws<char>(view, lay.b),
@@ -272,12 +252,6 @@ extern "C" int vecchia_status(const vecchia_view* view, void* stream, int64_t* f
     e = hipMemcpy(st, ws<uint64_t>(view, lay.status), sizeof(st), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "vecchia_status (copy)");
     if (first_bad_slot) *first_bad_slot = st[0] == kStatusNone ? -1 : (int64_t)st[0];
-    uint64_t flow_flag = 0;
-    e = hipMemcpy(&flow_flag, ws<uint64_t>(view, lay.status) + 4, sizeof(flow_flag), hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return hip_fail(e, "vecchia_status (copy)");
-    if (flow_flag)
-        return vecchia_set_error(VECCHIA_EHIP, "vecchia_forward: a batch wait reached its limit; the last forward "
-                                               "result is invalid");
     if (st[0] != kStatusNone)
         return vecchia_set_error(VECCHIA_ENOTPD, "covariance not positive definite at storage position %llu (%llu points)",
                                  (unsigned long long)st[0], (unsigned long long)st[1]);

@@ -17,22 +17,25 @@ constexpr int kTile = 64;             // points per tile of the tiled layout
 constexpr uint64_t kStatusNone = ~0ull;
 
 // Lanes per point of the factor kernels, by precision and padded width.
-// Lane r of a group owns rows r, r+P, ...; chosen so that the packed lower
-// triangle of K_cc (P*R*(R+1)/2 values per lane, R = kp/P) stays in registers.
+// Lane r of a group owns rows r, r+P, ...; the packed lower triangle of K_cc
+// (P*R*(R+1)/2 values per lane, R = kp/P) stays in registers.  Groups of 4
+// exchange values with DPP quad permutes (VALU); FP64 at kp = 32 also uses 4
+// lanes, which needs the accumulation registers of one wave per SIMD (groups
+// of 8 would need ds_swizzle round trips through the LDS unit instead).
 __host__ __device__ constexpr int factor_lanes(int precision, int kp) {
-    return precision == VECCHIA_FP32 ? (kp <= 8 ? 1 : 4) : (kp <= 8 ? 1 : (kp <= 16 ? 4 : 8));
+    return kp <= 8 ? 1 : 4;
 }
 
-// Batch-completion counters of the dataflow forward: [0] chunk ticket,
-// [1 + m] chunks finished of the m-th batch of a launch.
-constexpr int kFlowMaxLevels = 8192;
-constexpr int kFlowWords = 1 + kFlowMaxLevels;
+// Waves per SIMD that the register allocation of a factor kernel must allow.
+__host__ __device__ constexpr int factor_min_waves(int elem_bytes, int kp) {
+    return elem_bytes == 8 && kp == 32 ? 1 : 2;
+}
 
 // Device workspace holding one factor.  Offsets are 256-byte aligned.
 struct Layout {
     int64_t ns = 0, ntiles = 0, nparts = 0;
     size_t esz = 0;
-    size_t b = 0, sigma = 0, l0 = 0, ldpart = 0, ld0 = 0, ldstage = 0, status = 0, flow = 0, redo = 0, total = 0;
+    size_t b = 0, sigma = 0, l0 = 0, ldpart = 0, ld0 = 0, ldstage = 0, status = 0, redo = 0, total = 0;
 };
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -58,9 +61,7 @@ inline Layout workspace_layout(int64_t n, int kp, int n0, int precision) {
     w.ldstage = off;
     off = align256(off + 2 * 256 * sizeof(double));
     w.status = off;
-    off = align256(off + 5 * sizeof(uint64_t));
-    w.flow = off;
-    off = align256(off + kFlowWords * sizeof(uint32_t));
+    off = align256(off + 8 * sizeof(uint64_t));
     w.redo = off;
     if (precision == VECCHIA_FP32) off = align256(off + (size_t)(w.ns > 0 ? w.ns : 1) * sizeof(uint32_t));
     w.total = off;
@@ -169,13 +170,6 @@ constexpr int64_t kRunMaxPoints = 2048;  // a batch this small joins a run
 hipError_t launch_forward_run(int precision, int kp, const int32_t* nbr, const void* b, const void* sigma,
                               const void* xi, void* v, int n0, const int32_t* level_ptr_dev, int l_begin, int l_end,
                               hipStream_t stream);
-// Dataflow forward over the batches [l_begin, l_end) in one launch (see
-// forward_flow_kernel); `flow` holds kFlowWords counters, reset here; a wait
-// that reaches its limit sets *flag (status word 4 of the workspace).
-constexpr int kFlowChunk = 256;          // points per chunk (one workgroup)
-hipError_t launch_forward_flow(int precision, int kp, const int32_t* nbr, const void* b, const void* sigma,
-                               const void* xi, void* v, int n0, const int32_t* level_ptr_dev, int l_begin, int l_end,
-                               int64_t s_begin, int64_t s_end, uint32_t* flow, uint64_t* flag, hipStream_t stream);
 hipError_t launch_inverse_dense(int precision, const double* l0, int n0, const void* v, void* xi, hipStream_t stream);
 hipError_t launch_inverse_sparse(int precision, int kp, const int32_t* nbr, const void* b, const void* sigma,
                                  const void* v, void* xi, int n0, int64_t ns, hipStream_t stream);

@@ -23,7 +23,9 @@ __global__ __launch_bounds__(kDenseThreads) void factor_dense_kernel(const TX* _
         status[1] = 0;             // failing points
         status[2] = 0;             // FP32 path: points recomputed in double
         status[3] = 0;             // their sum of log sigma, fixed point
-        status[4] = 0;             // a dataflow forward wait reached its limit
+        status[4] = 0;             // unused
+        status[5] = 0;             // FP32 policy sample: points that would be recomputed in double
+        status[6] = 0;             // FP32 policy sample: points looked at
     }
     if (i < n0) {
         const double a0 = (double)x[i * 3 + 0], a1 = (double)x[i * 3 + 1], a2 = (double)x[i * 3 + 2];

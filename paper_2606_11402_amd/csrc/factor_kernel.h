@@ -44,7 +44,8 @@ struct FactorArgs {
     T* b;                  // tiled coefficients
     T* sigma;              // conditional standard deviation per sparse index
     double* ldpart;        // per-block sum of log sigma
-    uint64_t* status;      // [first bad position, bad count, redo count, redo log-sigma sum (fixed point)]
+    uint64_t* status;      // [first bad position, bad count, redo count, redo log-sigma sum (fixed point),
+                           //  unused, policy sample: flagged, looked at]
     uint32_t* redo;        // FP32 path: sparse indices recomputed in double
     int64_t ns;
     int64_t nblocks;
@@ -52,7 +53,21 @@ struct FactorArgs {
     Cov<T> cov;
     double diag;           // K_ii = sigma^2 + nugget, double
     double redo_ratio;     // FP32 path: recompute a point in double when a pivot < redo_ratio * K_ii
+    int64_t probe_stride;  // FP32 path: > 0 for the sample pass (every probe_stride-th block)
 };
+
+// FP32 path, precision policy.  A sample pass runs the float factor on every
+// kProbeStride-th block and counts, in status[5] and status[6], the points
+// it would send to the double recompute and the points it looked at.  When
+// more than three quarters would go (kernel values in float cannot resolve
+// these conditional variances, and the float pass would be wasted work), the
+// float pass is skipped and every point is computed in double.  The choice
+// depends only on the inputs, so results stay reproducible.
+constexpr int64_t kProbeStride = 64;
+__device__ __forceinline__ bool all_points_in_double(const uint64_t* status) {
+    const uint64_t flagged = status[5], sampled = status[6];
+    return sampled > 0 && 4 * flagged > 3 * sampled;
+}
 
 // Fixed-point scale of the log-sigma sum of recomputed points: integer
 // additions commute, so the sum does not depend on the order of the atomics.
@@ -289,19 +304,23 @@ __device__ __forceinline__ void factor_point(const TX* __restrict__ x, const int
 // One group of P lanes per sparse point, all points at once.  FP32 storage
 // (REFINE): a point whose pivots fail or fall below redo_ratio * K_ii is not
 // written here; it is appended to the redo list and recomputed in double by
-// factor_redo_kernel.
-#ifndef VK_FACTOR_MIN_WAVES
-#define VK_FACTOR_MIN_WAVES 2   // waves per SIMD the register allocation must allow
-#endif
-
-template <typename T, int K, int P, int KIND, bool REFINE>
-__global__ __launch_bounds__(kBlock, VK_FACTOR_MIN_WAVES) void factor_sparse_kernel(FactorArgs<T> a) {
+// factor_redo_kernel.  Each workgroup appends its points as one contiguous
+// run (one atomic per workgroup), so the list keeps the storage order of
+// neighbouring points and the recompute gathers stay local.  PROBE: the
+// policy sample pass (counts only, writes nothing else).
+template <typename T, int K, int P, int KIND, bool REFINE, bool PROBE>
+__global__ __launch_bounds__(kBlock, factor_min_waves(sizeof(T), K)) void factor_sparse_kernel(FactorArgs<T> a) {
     static_assert(K % P == 0, "K must be a multiple of P");
     constexpr int R = K / P;
     constexpr int PTS = kBlock / P;
     const int tid = threadIdx.x;
     const int r = tid % P;
-    const int64_t blk = xcd_block(blockIdx.x, a.nblocks);
+    constexpr bool probe = REFINE && PROBE;
+    const int64_t blk = probe ? (int64_t)blockIdx.x * a.probe_stride : xcd_block(blockIdx.x, a.nblocks);
+    if (REFINE && !probe && all_points_in_double(a.status)) {
+        if (tid == 0) a.ldpart[blk] = 0.0;            // every point goes to factor_redo_kernel
+        return;
+    }
     const int64_t sp_raw = blk * PTS + tid / P;
     const bool live = sp_raw < a.ns;
     const int64_t sp = live ? sp_raw : a.ns - 1;      // dead lanes mirror a live point
@@ -312,6 +331,22 @@ __global__ __launch_bounds__(kBlock, VK_FACTOR_MIN_WAVES) void factor_sparse_ker
     bool bad;
     factor_point<T, T, K, P, KIND, REFINE>(a.x, a.nbr, a.n0, sp, r, a.cov, a.diag, bv, s2, minpiv, bad);
     const bool redo = REFINE && (bad || minpiv < a.redo_ratio * a.diag);
+
+    if constexpr (probe) {
+        __shared__ unsigned counts[2];
+        if (tid == 0) counts[0] = counts[1] = 0u;
+        __syncthreads();
+        if (live && r == 0) {
+            atomicAdd(&counts[0], redo ? 1u : 0u);
+            atomicAdd(&counts[1], 1u);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            atomicAdd((unsigned long long*)&a.status[5], (unsigned long long)counts[0]);
+            atomicAdd((unsigned long long*)&a.status[6], (unsigned long long)counts[1]);
+        }
+        return;
+    }
 
     if (live && !redo) {
         static_for<0, R>([&](auto PI) {
@@ -326,9 +361,27 @@ __global__ __launch_bounds__(kBlock, VK_FACTOR_MIN_WAVES) void factor_sparse_ker
             }
         }
     }
-    if (live && redo && r == 0) {
-        const unsigned long long slot = atomicAdd((unsigned long long*)&a.status[2], 1ull);
-        a.redo[slot] = (uint32_t)sp;
+    if constexpr (REFINE) {
+        // the workgroup's recompute points as one run: rank within the
+        // workgroup by a prefix count, one atomic for the run's start
+        __shared__ unsigned wave_cnt[kBlock / 64];
+        __shared__ unsigned long long run_start;
+        const bool mine = live && redo && r == 0;
+        const uint64_t ballot = __ballot(mine);
+        const int lane = tid & 63, wave = tid >> 6;
+        if (lane == 0) wave_cnt[wave] = (unsigned)__popcll(ballot);
+        __syncthreads();
+        if (tid == 0) {
+            unsigned total = 0;
+            for (int w = 0; w < kBlock / 64; ++w) total += wave_cnt[w];
+            run_start = total ? atomicAdd((unsigned long long*)&a.status[2], (unsigned long long)total) : 0ull;
+        }
+        __syncthreads();
+        if (mine) {
+            unsigned before = (unsigned)__popcll(ballot & ((1ull << lane) - 1ull));
+            for (int w = 0; w < wave; ++w) before += wave_cnt[w];
+            a.redo[run_start + before] = (uint32_t)sp;
+        }
     }
     double lsum = (live && !redo && r == 0) ? 0.5 * log(s2) : 0.0;
     lsum = wave_sum_f64<T>(lsum);
@@ -343,19 +396,30 @@ __global__ __launch_bounds__(kBlock, VK_FACTOR_MIN_WAVES) void factor_sparse_ker
 }
 
 // FP32 storage: the listed points again, entirely in double (kernel values,
-// Cholesky, solves), results rounded to float.  A fixed grid walks the list;
-// log sigma of these points is added in fixed point to status[3].
+// Cholesky, solves), results rounded to float.  The grid covers every sparse
+// point (the list length is known only on the device); groups past the list
+// end leave at once.  log sigma: when every point is recomputed (policy) a
+// workgroup covers the same 64 points as the float pass would and writes its
+// double partial to ldpart; otherwise the workgroup adds its partial in
+// fixed point to status[3] with one atomic (integer sums commute).
 template <int K, int KIND>
-__global__ __launch_bounds__(kBlock) void factor_redo_kernel(FactorArgs<float> a, Cov<double> cov) {
+__global__ __launch_bounds__(kBlock, factor_min_waves(8, K)) void factor_redo_kernel(FactorArgs<float> a,
+                                                                                       Cov<double> cov) {
     constexpr int P = factor_lanes(VECCHIA_FP64, K);
     constexpr int R = K / P;
     constexpr int PTS = kBlock / P;
     const int tid = threadIdx.x;
     const int r = tid % P;
-    const int64_t count = (int64_t)a.status[2];
-    const int64_t groups = (int64_t)gridDim.x * PTS;
-    for (int64_t e = (int64_t)blockIdx.x * PTS + tid / P; e < count; e += groups) {
-        const int64_t sp = a.redo[e];
+    const bool direct = all_points_in_double(a.status);
+    const int64_t count = direct ? a.ns : (int64_t)a.status[2];
+    if (direct && blockIdx.x == 0 && tid == 0) a.status[2] = (uint64_t)a.ns;   // recompute count for the host
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    if (blk * PTS >= count) return;
+    const int64_t e = blk * PTS + tid / P;
+    double lsum = 0.0;
+    long long lfix = 0;
+    if (e < count) {
+        const int64_t sp = direct ? e : (int64_t)a.redo[e];
         const int64_t base = (sp >> 6) * (int64_t)K * kTile + (sp & 63);
         double bv[R];
         double s2, minpiv;
@@ -370,10 +434,31 @@ __global__ __launch_bounds__(kBlock) void factor_redo_kernel(FactorArgs<float> a
             if (bad) {
                 atomicMin((unsigned long long*)&a.status[0], (unsigned long long)(a.n0 + sp));
                 atomicAdd((unsigned long long*)&a.status[1], 1ull);
+            } else if (direct) {
+                lsum = 0.5 * log(s2);
             } else {
-                const long long fix = __double2ll_rn(0.5 * log(s2) * kFixScale);
-                atomicAdd((unsigned long long*)&a.status[3], (unsigned long long)fix);
+                lfix = __double2ll_rn(0.5 * log(s2) * kFixScale);
             }
+        }
+    }
+    __shared__ double part[kBlock / 64];
+    __shared__ long long part_fix[kBlock / 64];
+    lsum = wave_sum_f64<double>(lsum);
+    for (int off = 32; off > 0; off >>= 1) lfix += __shfl_xor(lfix, off, 64);
+    if ((tid & 63) == 0) {
+        part[tid >> 6] = lsum;
+        part_fix[tid >> 6] = lfix;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        if (direct) {
+            double s = 0.0;
+            for (int w = 0; w < kBlock / 64; ++w) s += part[w];
+            a.ldpart[blk] = s;
+        } else {
+            long long f = 0;
+            for (int w = 0; w < kBlock / 64; ++w) f += part_fix[w];
+            if (f) atomicAdd((unsigned long long*)&a.status[3], (unsigned long long)f);
         }
     }
 }
@@ -395,17 +480,27 @@ hipError_t launch_factor_sparse_t(const FactorLaunch& L, hipStream_t stream) {
     a.cov = make_cov<T>(L.kern);
     a.diag = L.kern.sigma * L.kern.sigma + L.kern.nugget;
     a.redo_ratio = L.redo_ratio;
+    a.probe_stride = 0;
     const int64_t pts = kBlock / P;
     a.nblocks = (L.ns + pts - 1) / pts;
     if (a.nblocks == 0) return hipSuccess;
     constexpr bool refine = sizeof(T) == 4;
-    hipLaunchKernelGGL((factor_sparse_kernel<T, K, P, KIND, refine>), dim3((unsigned)a.nblocks), dim3(kBlock), 0,
-                       stream, a);
+    if (refine && L.redo_ratio > 0.0) {
+        FactorArgs<T> pa = a;
+        pa.probe_stride = kProbeStride;
+        const int64_t probe_blocks = (a.nblocks + kProbeStride - 1) / kProbeStride;
+        hipLaunchKernelGGL((factor_sparse_kernel<T, K, P, KIND, refine, true>), dim3((unsigned)probe_blocks),
+                           dim3(kBlock), 0, stream, pa);
+        hipError_t pe = hipGetLastError();
+        if (pe != hipSuccess) return pe;
+    }
+    hipLaunchKernelGGL((factor_sparse_kernel<T, K, P, KIND, refine, false>), dim3((unsigned)a.nblocks), dim3(kBlock),
+                       0, stream, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !refine) return e;
     if constexpr (refine) {
         constexpr int P64 = factor_lanes(VECCHIA_FP64, K);
-        const int64_t blocks = std::min<int64_t>((a.nblocks * P64 + P - 1) / P, 1024);
+        const int64_t blocks = (L.ns * P64 + kBlock - 1) / kBlock;
         hipLaunchKernelGGL((factor_redo_kernel<K, KIND>), dim3((unsigned)blocks), dim3(kBlock), 0, stream, a,
                            make_cov<double>(L.kern));
         e = hipGetLastError();

@@ -1,9 +1,9 @@
-"""The dataflow forward (one launch over many batches: chunk tickets and
-batch-completion counters) against the forward with one launch per batch.
-Both evaluate every v_i with the same operations in the same order, so they
-must agree bit for bit; the per-batch forward is itself checked against the
-oracle in test_gpu_parity.py.  Sizes are chosen so that batches exceed the
-small-batch threshold and the dataflow launch really runs."""
+"""The forward as the library runs it (one workgroup per run of small
+batches, one launch per larger batch) against the forward with one launch per
+batch for every batch.  Both evaluate every v_i with the same operations in
+the same order, so they must agree bit for bit; the per-batch forward is
+itself checked against the oracle in test_gpu_parity.py.  Sizes are chosen so
+that both kinds of batches occur."""
 import numpy as np
 import pytest
 import torch
@@ -18,18 +18,18 @@ SMALL_BATCH = 2048   # batches up to this size go to the one-workgroup run kerne
 
 @pytest.mark.parametrize("wl,n,k,precision", [(3, 1 << 21, 32, FP32), (2, 1 << 20, 16, FP32),
                                               (1, 1 << 19, 8, FP64)])
-def test_dataflow_forward_matches_per_batch(wl, n, k, precision):
+def test_forward_paths_match_per_batch(wl, n, k, precision):
     w = workloads.WORKLOADS[wl]
-    print("dataflow forward: workload", wl, "n", n, "k", k, "precision", precision, flush=True)
+    print("forward paths: workload", wl, "n", n, "k", k, "precision", precision, flush=True)
     g = Graph(w.points(n), k, w.n0)
     sizes = np.diff(np.asarray(g.level_ptr)[1:])
-    assert (sizes > SMALL_BATCH).sum() >= 2, "no batch large enough for the dataflow launch"
+    assert (sizes > SMALL_BATCH).sum() >= 2 and (sizes <= SMALL_BATCH).sum() >= 2
     dg = g.to_device(precision, "cuda:0")
     fac = Factor(dg, KernelParams(w.kind, w.sigma, w.ell, w.nugget))
     xi = torch.from_numpy(g.to_storage(w.xi(n))).to(dg.dtype).cuda()
     v_batch = fac.forward(xi, per_batch=True)
     v_flow = [fac.forward(xi) for _ in range(3)]
-    fac.status()          # raises if a dataflow wait reached its limit
+    fac.status()
     for v in v_flow:
         assert torch.equal(v, v_batch)
     if precision == FP64:
@@ -37,9 +37,8 @@ def test_dataflow_forward_matches_per_batch(wl, n, k, precision):
         assert ((xi_back - xi).abs().max() / xi.abs().max()).item() < 1e-10
 
 
-def test_dataflow_forward_with_empty_batches_in_view():
-    """An empty batch in level_ptr splits the dataflow range; the result
-    stays that of the per-batch forward."""
+def test_forward_with_empty_batches_in_view():
+    """An empty batch in level_ptr (allowed by the view) changes nothing."""
     w = workloads.WORKLOADS[2]
     n, k = 1 << 19, 16
     g = Graph(w.points(n), k, w.n0)
