@@ -54,6 +54,17 @@ def factor_bytes_per_point(k, esz):
     return 4 * k + 3 * esz * k + 3 * esz + esz * k + esz
 
 
+def precision_note(precision, n_redo, ns):
+    if precision != 1:
+        return "fp64 throughout"
+    head = "fp32 storage of b, sigma, v; forward in fp32; logdet in fp64 (compensated); "
+    if n_redo == ns:
+        return head + ("factor arithmetic in fp64 for every point: the sampled policy found that float kernel "
+                       "values cannot resolve these conditional variances")
+    return head + ("factor in fp32 with fp64 pivots and one refinement step; %d of %d points recomputed in fp64"
+                   % (n_redo, ns))
+
+
 def apply_bytes_per_point(k, esz):
     # neighbour index + coefficient + gathered v per neighbour, sigma, xi/v in, v/xi out
     return 4 * k + esz * k + esz * k + 3 * esz
@@ -130,6 +141,10 @@ def main():
     ap.add_argument("--cpu-passes", type=int, default=8)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a 1 GiB device copy (counter calibration) and exit")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the comparisons (FP64 path on the same workload, k=16 radial in both precisions)")
+    ap.add_argument("--serve-requests", type=int, default=128,
+                    help="requests of the serving measurement (0 skips it)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -219,9 +234,21 @@ def main():
 
     ns = n - n0
     steps = args.steps
-    f_ms = prof["factor_sparse"][0] / prof["factor_sparse"][1]
-    flops = factor_flops_per_point(k, w.kind, precision == FP32) * ns
-    f_tflops = flops / (f_ms * 1e-3) / 1e12
+    avg = lambda name: prof[name][0] / prof[name][1] if name in prof else 0.0
+    sparse_ms, redo_ms, probe_ms = avg("factor_sparse"), avg("factor_redo"), avg("factor_probe")
+    n_bad, n_redo = fac.counts()
+    # the dominant factor kernel: the float pass (every point, with refinement)
+    # or the double pass (the recomputed points, no refinement)
+    if redo_ms > sparse_ms:
+        dom, f_ms, units = "factor_redo", redo_ms, n_redo
+        fpp = factor_flops_per_point(k, w.kind, False)
+        dom_desc = "factor_redo (Eq. 2 in FP64 for the points float cannot resolve: gather, K_cc, Cholesky, solves)"
+    else:
+        dom, f_ms, units = "factor_sparse", sparse_ms, ns
+        fpp = factor_flops_per_point(k, w.kind, precision == FP32)
+        dom_desc = "factor_sparse (Eq. 2 per point: gather, K_cc, Cholesky, solves, refinement)"
+    flops = fpp * units
+    f_tflops = flops / (f_ms * 1e-3) / 1e12 if f_ms > 0 else 0.0
     fwd_ms = sum(t for name, (t, _) in prof.items() if name.startswith("forward_")) / steps
     ld_ms = prof["logdet"][0] / prof["logdet"][1]
     inv_ms = (prof["inverse_sparse"][0] + prof.get("inverse_dense", (0.0, 0))[0]) / steps
@@ -235,19 +262,19 @@ def main():
                     if name.startswith("forward_") and name != "forward_dense") / steps
     kp = 8 if k <= 8 else (16 if k <= 16 else 32)
     digest = source_digest(kernel_sources("f32" if precision == FP32 else "f64", kp))
-    tr = read_traffic("factor_sparse", w.name if args.n is None and args.k is None else None, digest)
+    tr = read_traffic(dom, w.name if args.n is None and args.k is None else None, digest)
     traffic, traffic_detail = None, None
     if tr is not None:
         traffic = tr["fetch_bytes"] + tr["write_bytes"]
         traffic_detail = {"fetch_bytes": tr["fetch_bytes"], "write_bytes": tr["write_bytes"],
                           "copy_scale_fetch": tr["copy_scale_fetch"], "copy_scale_write": tr["copy_scale_write"],
-                          "algorithmic_bytes": factor_bytes_per_point(k, esz) * ns, "summary": tr["summary"]}
+                          "algorithmic_bytes": factor_bytes_per_point(k, esz) * units, "summary": tr["summary"]}
 
     roofline = {
-        "kernel": "factor_sparse (Eq. 2 per point: gather, K_cc, Cholesky, solves, refinement)",
+        "kernel": dom_desc,
         "bound": "alu", "achieved": round(f_tflops, 3), "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
         "frac": round(f_tflops / VALU_PEAK_TFLOPS, 4), "traffic": traffic,
-        "flops_per_point": factor_flops_per_point(k, w.kind, precision == FP32), "points_per_launch": ns,
+        "flops_per_point": fpp, "points_per_launch": units,
         "avg_launch_ms": round(f_ms, 4), "source_digest": digest, "traffic_detail": traffic_detail,
     }
     others = {
@@ -267,14 +294,16 @@ def main():
     out = {
         "metric": METRIC, "value": value, "unit": "points/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32" if precision == FP32 else "f64", "data": "synthetic",
+        "vs_baseline": None, "dtype": ("f32+f64" if n_redo > 0 else "f32") if precision == FP32 else "f64",
+        "data": "synthetic",
         "config": {"workload": w.name, "n": n, "k": k, "n0": n0, "kernel": ["EXP", "M32", "SE"][w.kind],
                    "ell": w.ell, "sigma": w.sigma, "nugget": w.nugget,
-                   "precision": "fp32 storage/arithmetic, fp64 pivots, variances and logdet" if precision == FP32
-                   else "fp64", "levels": g.n_levels, "points_recomputed_fp64": n_redo},
+                   "precision": precision_note(precision, n_redo, ns), "levels": g.n_levels,
+                   "points_recomputed_fp64": n_redo},
         "roofline": roofline,
         "rooflines_other": others,
-        "ops_ms": {"factor_sparse": round(f_ms, 4), "forward": round(fwd_ms, 4), "forward_levels_only": round(levels_ms, 4),
+        "ops_ms": {"factor_probe": round(probe_ms, 4), "factor_sparse": round(sparse_ms, 4),
+                   "factor_redo": round(redo_ms, 4), "forward": round(fwd_ms, 4), "forward_levels_only": round(levels_ms, 4),
                    "logdet": round(ld_ms, 4), "inverse": round(inv_ms, 4),
                    "instrumented_step_ms": round((tp1 - tp0) * 1e3 / steps, 3)},
         "graph_build_s": round(graph_s, 2), "graph_phases_s": {a: round(b, 2) for a, b in g.build_times().items()},
@@ -283,9 +312,160 @@ def main():
     # ---- sampled check against the oracle at full size (outside the timed region)
     if not args.no_check:
         out["check"] = sampled_check(g, fac, v, xi, kern, w, n, k, n0)
+    if not args.no_compare:
+        # the plain FP64 path on the same points, graph and white noise
+        v32, ld32 = v.double(), float(ld.item())
+        del fac, dg, v
+        torch.cuda.empty_cache()
+        out["fp64_path_same_workload"] = compare_fp64(g, kern, xi_in, v32, ld32, args.steps, dev)
+        del v32
+        torch.cuda.empty_cache()
+        out["k16_radial"] = k16_radial(args.steps, dev)
+        if args.workload == 3 and args.k is None:
+            out["k16_same_distribution"] = same_distribution_k16(w, n, args.steps, dev, args.threads)
+    copy_gbs = copy_bandwidth(dev)
+    out["copy_bandwidth_GBs"] = round(copy_gbs, 1)
+    out["rooflines_other"]["forward+logdet"]["frac_of_copy"] = round(fl_gbs / copy_gbs, 4)
+    if args.serve_requests > 0:
+        out["serving"] = serving_run(args.serve_requests)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, k, n0, args.cpu_sample, args.cpu_passes)
     print(json.dumps(out), flush=True)
+
+
+def copy_bandwidth(dev, nbytes=1 << 30, reps=10):
+    """Device-to-device copy of 1 GiB (read + write), GB/s, HIP events."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    return 2 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+
+
+def same_distribution_k16(w, n, steps, dev, threads):
+    """The headline distribution and kernel at k = 16 (graph rebuilt)."""
+    import torch
+    from paper_2606_11402_amd import FP32, Factor, Graph, KernelParams
+    from paper_2606_11402_amd import vecchia as vmod
+    g = Graph(w.points(n), 16, w.n0, n_threads=threads)
+    dg = g.to_device(FP32, dev)
+    xi = torch.from_numpy(g.to_storage(w.xi(n))).float().to(dev)
+    v = torch.empty(n, dtype=torch.float32, device=dev)
+    ld = torch.empty(1, dtype=torch.float64, device=dev)
+    fac = Factor(dg, KernelParams(w.kind, w.sigma, w.ell, w.nugget))
+    ms = time_steps(fac, xi, v, ld, steps)
+    vmod.profile_reset()
+    vmod.profile_enable(True)
+    for _ in range(steps):
+        fac.forward(xi, out=v)
+        fac.logdet(out=ld)
+    prof = vmod.profile_read()
+    vmod.profile_enable(False)
+    fl_ms = sum(t for name, (t, _) in prof.items() if name.startswith("forward_") or name == "logdet") / steps
+    bpp = apply_bytes_per_point(16, 4) + 4
+    gbs = bpp * (n - w.n0) / (fl_ms * 1e-3) / 1e9
+    res = {"k": 16, "ms_per_step": round(ms, 3), "points_per_s": n / (ms * 1e-3),
+           "points_recomputed_fp64": fac.counts()[1], "forward+logdet_ms": round(fl_ms, 4),
+           "forward+logdet_GBs": round(gbs, 1), "forward+logdet_frac": round(gbs / HBM_PEAK_GBS, 4),
+           "levels": g.n_levels}
+    log("k16 same distribution:", res)
+    return res
+
+
+def time_steps(fac, xi, v, ld, steps):
+    import torch
+    for _ in range(2):
+        fac.refactor()
+        fac.forward(xi, out=v)
+        fac.logdet(out=ld)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fac.refactor()
+        fac.forward(xi, out=v)
+        fac.logdet(out=ld)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def compare_fp64(g, kern, xi_in, v32, ld32, steps, dev):
+    """Plain FP64 path (FP64 storage and arithmetic throughout) on the same
+    graph and white noise; the FP32 path's v and logdet against it."""
+    import torch
+    from paper_2606_11402_amd import FP64, Factor
+    dg = g.to_device(FP64, dev)
+    xi = torch.from_numpy(g.to_storage(xi_in)).double().to(dev)
+    v = torch.empty(g.n, dtype=torch.float64, device=dev)
+    ld = torch.empty(1, dtype=torch.float64, device=dev)
+    fac = Factor(dg, kern)
+    ms = time_steps(fac, xi, v, ld, steps)
+    fac.status()
+    ld64 = float(ld.item())
+    v_rel = float(((v32 - v).abs().max() / v.abs().max()).item())
+    log("fp64 path: %.3f ms/step" % ms)
+    return {"ms_per_step": round(ms, 3), "points_per_s": g.n / (ms * 1e-3),
+            "fp32_path_v_rel_err": v_rel, "fp32_path_logdet_rel_err": abs(ld32 - ld64) / abs(ld64),
+            "note": "same points, graph and xi; errors of the FP32 path measured against this FP64 path"}
+
+
+def k16_radial(steps, dev):
+    """The k = 16 configuration (2^20 radial points, Matern-3/2, ell = 0.05):
+    FP32 path and plain FP64 path, same graph and white noise."""
+    import torch
+    import workloads
+    from paper_2606_11402_amd import FP32, FP64, Factor, Graph, KernelParams
+    w = workloads.WORKLOADS[2]
+    g = Graph(w.points(w.n), w.k, w.n0)
+    kern = KernelParams(w.kind, w.sigma, w.ell, w.nugget)
+    res, outs = {}, {}
+    for prec, name in ((FP32, "fp32"), (FP64, "fp64")):
+        dg = g.to_device(prec, dev)
+        xi = torch.from_numpy(g.to_storage(w.xi(w.n))).to(dg.dtype).to(dev)
+        v = torch.empty(g.n, dtype=dg.dtype, device=dev)
+        ld = torch.empty(1, dtype=torch.float64, device=dev)
+        fac = Factor(dg, kern)
+        ms = time_steps(fac, xi, v, ld, steps)
+        fac.status()
+        res[name] = {"ms_per_step": round(ms, 3), "points_per_s": g.n / (ms * 1e-3),
+                     "points_recomputed_fp64": fac.counts()[1]}
+        outs[name] = (v.double(), float(ld.item()))
+    v32, l32 = outs["fp32"]
+    v64, l64 = outs["fp64"]
+    res["fp32_vs_fp64"] = {"v_rel": float(((v32 - v64).abs().max() / v64.abs().max()).item()),
+                           "logdet_rel": abs(l32 - l64) / abs(l64)}
+    res["config"] = {"workload": w.name, "n": w.n, "k": w.k, "kernel": "M32", "ell": w.ell}
+    log("k16 radial:", res)
+    return res
+
+
+def serving_run(n_requests):
+    """A prefix of the serving request stream (N log-uniform in [1e3, 1e6],
+    k in {8, 16, 32}, ell ~ U(0.01, 0.2), forward / inverse / logdet, FP32):
+    closed-loop capacity, then Poisson arrivals at 0.7 of it."""
+    import workloads
+    from paper_2606_11402_amd.serve import Server, run_stream
+    reqs = workloads.request_stream(n_requests, rate=1.0)
+    budget = 8 << 30
+    srv = Server(budget, n_streams=8, graph_workers=14)
+    closed = run_stream(reqs, srv, rate=None)
+    srv.close()
+    srv = Server(budget, n_streams=8, graph_workers=14)
+    lam = 0.7 * closed["req_per_s"]
+    opened = run_stream(reqs, srv, rate=lam)
+    srv.close()
+    keep = ("req_per_s", "points_per_s", "latency_p50_s", "latency_p99_s", "graph_p50_s", "graph_p99_s",
+            "queue_p50_s", "device_p50_s", "device_p99_s", "peak_hbm_bytes")
+    log("serving: capacity %.1f req/s, p50 %.3fs p99 %.3fs at 0.7x" % (closed["req_per_s"], opened["latency_p50_s"],
+                                                                     opened["latency_p99_s"]))
+    return {"requests": n_requests, "hbm_budget_bytes": budget, "closed_loop": {a: closed[a] for a in keep},
+            "open_loop_0.7": dict({a: opened[a] for a in keep}, lambda_req_per_s=lam)}
 
 
 def sampled_check(g, fac, v, xi, kern, w, n, k, n0, samples=256):

@@ -53,28 +53,59 @@ __global__ __launch_bounds__(kBlock) void apply_kernel(const int32_t* __restrict
 // A run of consecutive small batches [l_begin, l_end) in one workgroup: the
 // batches are processed in order with a workgroup barrier between them (the
 // barrier orders the global writes of batch l before the gathers of batch
-// l + 1 inside the workgroup), which replaces one launch per batch.
+// l + 1 inside the workgroup), which replaces one launch per batch.  A
+// thread's first point of the next batch has its row (neighbour indices,
+// coefficients, sigma, xi: nothing that depends on v) loaded before the
+// barrier, so each batch costs one dependent memory round trip (the gather)
+// instead of two.
 template <typename T, int KP>
 __global__ __launch_bounds__(kRunThreads) void forward_run_kernel(const int32_t* __restrict__ nbr,
                                                                   const T* __restrict__ b, const T* __restrict__ sig,
                                                                   const T* __restrict__ xi, T* v, int n0,
                                                                   const int32_t* __restrict__ level_ptr, int l_begin,
                                                                   int l_end) {
-    for (int l = l_begin; l < l_end; ++l) {
-        const int64_t s_begin = level_ptr[l] - n0, s_end = level_ptr[l + 1] - n0;
-        for (int64_t sp = s_begin + threadIdx.x; sp < s_end; sp += kRunThreads) {
-            const int64_t base = (sp >> 6) * (int64_t)KP * kTile + (sp & 63);
-            T acc = T(0);
+    int32_t idx[KP];
+    T w[KP];
+    T sg = T(0), x = T(0);
+    auto load_row = [&](int64_t sp) {
+        const int64_t base = (sp >> 6) * (int64_t)KP * kTile + (sp & 63);
 #pragma unroll
-            for (int m = 0; m < KP; ++m) {
-                const int32_t j = nbr[base + m * kTile];
-                const T w = b[base + m * kTile];
-                const T vj = v[j >= 0 ? j : 0];
-                acc = fma(w, j >= 0 ? vj : T(0), acc);
-            }
-            v[n0 + sp] = fma(sig[sp], xi[n0 + sp], acc);
+        for (int m = 0; m < KP; ++m) {
+            idx[m] = nbr[base + m * kTile];
+            w[m] = b[base + m * kTile];
         }
+        sg = sig[sp];
+        x = xi[n0 + sp];
+    };
+    auto finish_row = [&](int64_t sp) {
+        T acc = T(0);
+#pragma unroll
+        for (int m = 0; m < KP; ++m) {
+            const int32_t j = idx[m];
+            const T vj = v[j >= 0 ? j : 0];
+            acc = fma(w[m], j >= 0 ? vj : T(0), acc);
+        }
+        v[n0 + sp] = fma(sg, x, acc);
+    };
+    int64_t s0 = (int64_t)level_ptr[l_begin] - n0, s1 = (int64_t)level_ptr[l_begin + 1] - n0;
+    bool have = s0 + (int64_t)threadIdx.x < s1;
+    if (have) load_row(s0 + threadIdx.x);
+    for (int l = l_begin; l < l_end; ++l) {
+        if (have) finish_row(s0 + threadIdx.x);
+        for (int64_t sp = s0 + threadIdx.x + kRunThreads; sp < s1; sp += kRunThreads) {
+            load_row(sp);
+            finish_row(sp);
+        }
+        int64_t t0 = s1, t1 = s1;
+        if (l + 1 < l_end) {
+            t0 = (int64_t)level_ptr[l + 1] - n0;
+            t1 = (int64_t)level_ptr[l + 2] - n0;
+        }
+        have = t0 + (int64_t)threadIdx.x < t1;
+        if (have) load_row(t0 + threadIdx.x);
         __syncthreads();
+        s0 = t0;
+        s1 = t1;
     }
 }
 

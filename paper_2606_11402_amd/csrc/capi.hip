@@ -159,8 +159,21 @@ extern "C" int vecchia_factor(vecchia_view* view, const vecchia_kernel* kern, vo
     }
     a.kern = *kern;
     if (lay.ns > 0) {
+        // FP32: the policy sample, the float pass and the double pass are
+        // timed apart; FP64 has the main pass only
+        if (view->precision == VECCHIA_FP32 && a.redo_ratio > 0.0) {
+            a.stages = kStageProbe;
+            e = timed("factor_probe", s, [&] { return launch_factor_sparse(a, s); });
+            if (e != hipSuccess) return hip_fail(e, "vecchia_factor (precision sample)");
+        }
+        a.stages = kStageMain;
         e = timed("factor_sparse", s, [&] { return launch_factor_sparse(a, s); });
         if (e != hipSuccess) return hip_fail(e, "vecchia_factor (sparse points)");
+        if (view->precision == VECCHIA_FP32) {
+            a.stages = kStageRedo;
+            e = timed("factor_redo", s, [&] { return launch_factor_sparse(a, s); });
+            if (e != hipSuccess) return hip_fail(e, "vecchia_factor (points recomputed in double)");
+        }
     }
     return VECCHIA_OK;
 }

@@ -75,6 +75,7 @@ inline Layout workspace_layout(int64_t n, int kp, int n0, int precision) {
 template <typename T>
 struct Cov {
     T s2;          // sigma^2
+    T sigma;       // sigma
     T ls2;         // log2(sigma^2)
     T m32_lin;     // -ln(2) sigma^2: sigma^2 (1 + a) = sigma^2 + m32_lin * (-a log2(e))
     T inv_ell;     // 1/ell
@@ -90,6 +91,7 @@ inline Cov<T> make_cov(const vecchia_kernel& k) {
     const double log2e = 1.4426950408889634, sqrt3 = 1.7320508075688772;
     Cov<T> c;
     c.s2 = (T)(k.sigma * k.sigma);
+    c.sigma = (T)k.sigma;
     c.ls2 = (T)std::log2(k.sigma * k.sigma);
     c.m32_lin = (T)(-0.6931471805599453 * k.sigma * k.sigma);
     c.inv_ell = (T)(1.0 / k.ell);
@@ -158,7 +160,9 @@ struct FactorLaunch {
     uint32_t* redo;
     double redo_ratio;
     vecchia_kernel kern;
+    int stages;            // bit mask of kStage* launched by this call
 };
+constexpr int kStageProbe = 1, kStageMain = 2, kStageRedo = 4;   // FP32: sample, float pass, double pass
 hipError_t launch_factor_sparse(const FactorLaunch& a, hipStream_t stream);
 hipError_t launch_factor_dense(int precision, int kind, const void* x, int n0, const vecchia_kernel& kern,
                                double* l0, double* ld0, uint64_t* status, hipStream_t stream);

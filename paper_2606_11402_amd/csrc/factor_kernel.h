@@ -158,6 +158,46 @@ __device__ __forceinline__ void assemble_kcc(const T* c0, const T* c1, const T* 
     });
 }
 
+// exp(z) for |z| <= 1 as exp(z/2)^2, exp(z/2) by its Taylor series to
+// degree 14 (coefficients 1/(i! 2^i), Horner in z): within about 2 units of
+// double roundoff on that interval, no range reduction.
+__device__ __forceinline__ double exp_small(double z) {
+    double p = 1.0 / 1428329123020800.0;                // 1/(14! 2^14)
+    p = fma(p, z, 1.0 / 51011754393600.0);              // 1/(13! 2^13)
+    p = fma(p, z, 1.0 / 1961990553600.0);               // 1/(12! 2^12)
+    p = fma(p, z, 1.0 / 81749606400.0);
+    p = fma(p, z, 1.0 / 3715891200.0);
+    p = fma(p, z, 1.0 / 185794560.0);
+    p = fma(p, z, 1.0 / 10321920.0);
+    p = fma(p, z, 1.0 / 645120.0);
+    p = fma(p, z, 1.0 / 46080.0);
+    p = fma(p, z, 1.0 / 3840.0);
+    p = fma(p, z, 1.0 / 384.0);
+    p = fma(p, z, 1.0 / 48.0);
+    p = fma(p, z, 1.0 / 8.0);
+    p = fma(p, z, 0.5);
+    p = fma(p, z, 1.0);
+    return p * p;
+}
+
+// K_cc of the squared-exponential kernel in product form (see factor_point).
+template <typename T, int K, int P>
+__device__ __forceinline__ void assemble_kcc_se_product(const T* w0, const T* w1, const T* w2, const T* a, T* A) {
+    constexpr int R = K / P;
+    static_for<0, K>([&](auto LI) {
+        constexpr int l = LI, pl = l / P, rl = l % P;
+        const T y0 = group_bcast<P, rl>(w0[pl]);
+        const T y1 = group_bcast<P, rl>(w1[pl]);
+        const T y2 = group_bcast<P, rl>(w2[pl]);
+        const T al = group_bcast<P, rl>(a[pl]);
+        static_for<pl, R>([&](auto PI) {
+            constexpr int p = PI;
+            const T z = fma(w0[p], y0, fma(w1[p], y1, w2[p] * y2));
+            A[row_off<P>(p) + l] = (a[p] * al) * exp_small(z);
+        });
+    });
+}
+
 // Right-looking Cholesky of K_cc in place: A receives the strictly lower
 // part of L (zero elsewhere), Inv[p] = 1/L_ii of the lane's rows.  Pivots
 // d_j = K_jj - sum_m L_jm^2 live in Dg (double) for both storage types.
@@ -214,14 +254,41 @@ __device__ __forceinline__ void factor_point(const TX* __restrict__ x, const int
     gather_rows<T, TX, K, P>(x, nbr, base, r, c0, c1, c2, ok);
 
     T A[NA];
-    assemble_kcc<T, K, P, KIND>(c0, c1, c2, ok, r, cov, A);
     T kc[R];
     double Dg[R];
-    static_for<0, R>([&](auto PI) {
-        constexpr int p = PI;
-        kc[p] = cov_r2<KIND>(sqdist3(c0[p], c1[p], c2[p], t0, t1, t2), cov);
-        Dg[p] = ok[p] ? diag : 1.0;
-    });
+    static_for<0, R>([&](auto PI) { Dg[(int)PI] = ok[(int)PI] ? diag : 1.0; });
+    if constexpr (KIND == 2 && sizeof(T) == 8) {
+        // Squared exponential in double, product form around the target:
+        // with w = (x - t) / ell, K_pl = a_p a_l exp(w_p . w_l) and
+        // a_p = sigma exp(-|w_p|^2 / 2), the target column k_p = sigma a_p.
+        // A product adds no cancellation, and when every |w|^2 in the wave is
+        // at most 1 the exponential of w_p . w_l is a short series (no range
+        // reduction): R exponentials per lane instead of one per entry.
+        // Padded neighbours get a = 0 and w = 0 (identity row and column).
+        T w0[R], w1[R], w2[R], a[R];
+        bool near = true;
+        static_for<0, R>([&](auto PI) {
+            constexpr int p = PI;
+            w0[p] = ok[p] ? (c0[p] - t0) * cov.inv_ell : T(0);
+            w1[p] = ok[p] ? (c1[p] - t1) * cov.inv_ell : T(0);
+            w2[p] = ok[p] ? (c2[p] - t2) * cov.inv_ell : T(0);
+            const T q = w0[p] * w0[p] + w1[p] * w1[p] + w2[p] * w2[p];
+            near = near && q <= T(1);
+            a[p] = ok[p] ? cov.sigma * exp(T(-0.5) * q) : T(0);
+            kc[p] = cov.sigma * a[p];
+        });
+        if (__all(near)) {
+            assemble_kcc_se_product<T, K, P>(w0, w1, w2, a, A);
+        } else {
+            assemble_kcc<T, K, P, KIND>(c0, c1, c2, ok, r, cov, A);
+        }
+    } else {
+        assemble_kcc<T, K, P, KIND>(c0, c1, c2, ok, r, cov, A);
+        static_for<0, R>([&](auto PI) {
+            constexpr int p = PI;
+            kc[p] = cov_r2<KIND>(sqdist3(c0[p], c1[p], c2[p], t0, t1, t2), cov);
+        });
+    }
 
     T Inv[R];
     bool bad = false;
@@ -485,7 +552,7 @@ hipError_t launch_factor_sparse_t(const FactorLaunch& L, hipStream_t stream) {
     a.nblocks = (L.ns + pts - 1) / pts;
     if (a.nblocks == 0) return hipSuccess;
     constexpr bool refine = sizeof(T) == 4;
-    if (refine && L.redo_ratio > 0.0) {
+    if (refine && L.redo_ratio > 0.0 && (L.stages & kStageProbe)) {
         FactorArgs<T> pa = a;
         pa.probe_stride = kProbeStride;
         const int64_t probe_blocks = (a.nblocks + kProbeStride - 1) / kProbeStride;
@@ -494,10 +561,13 @@ hipError_t launch_factor_sparse_t(const FactorLaunch& L, hipStream_t stream) {
         hipError_t pe = hipGetLastError();
         if (pe != hipSuccess) return pe;
     }
-    hipLaunchKernelGGL((factor_sparse_kernel<T, K, P, KIND, refine, false>), dim3((unsigned)a.nblocks), dim3(kBlock),
-                       0, stream, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !refine) return e;
+    hipError_t e = hipSuccess;
+    if (L.stages & kStageMain) {
+        hipLaunchKernelGGL((factor_sparse_kernel<T, K, P, KIND, refine, false>), dim3((unsigned)a.nblocks),
+                           dim3(kBlock), 0, stream, a);
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess || !refine || !(L.stages & kStageRedo)) return e;
     if constexpr (refine) {
         constexpr int P64 = factor_lanes(VECCHIA_FP64, K);
         const int64_t blocks = (L.ns * P64 + kBlock - 1) / kBlock;

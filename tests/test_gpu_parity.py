@@ -131,6 +131,21 @@ def test_c2_shape_radial_m32(precision):
     check_against_oracle(x, w.k, 128, Kernel(M32, 1.0, 0.05), precision, w.xi(n), limited=limited)
 
 
+def test_se_product_form_fp64():
+    """Dense points against ell (every neighbour within ell of its target for
+    most points, not all): the double factor assembles the squared-exponential
+    K_cc in product form with a short exponential series where a whole wave
+    qualifies and by direct evaluation elsewhere; parity at the FP64 bar."""
+    n, k = 1 << 15, 32
+    x = workloads.uniform(n, 91)
+    kern = Kernel(SE, 1.0, 0.15, 1e-6)
+    og = oracle.build_graph(x, k, 128)
+    w2 = np.sum((og.xs[og.nbr] - og.xs[128:, None, :]) ** 2, axis=-1) / kern.ell ** 2
+    frac = (w2.max(axis=1) <= 1.0).mean()
+    assert 0.8 < frac < 0.99                               # both assemblies occur
+    check_against_oracle(x, k, 128, kern, FP64, workloads.white_noise(n, 191), limited=("b", "xi_inverse"))
+
+
 def test_dimension_one_and_two():
     for d in (1, 2):
         x = np.random.default_rng(50 + d).random((900, d))
