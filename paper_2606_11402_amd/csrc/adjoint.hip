@@ -174,7 +174,8 @@ __global__ __launch_bounds__(kBlock) void adj_theta_kernel(AdjArgs<TS> a) {
         constexpr int p = PI;
         const int32_t j = a.nbr[base + (int64_t)(p * P + r) * kTile];
         bq[p] = (double)a.b[base + (int64_t)(p * P + r) * kTile];
-        bbar[p] = j >= 0 ? omega * (double)a.v[j] : 0.0;
+        const double vj = (double)a.v[j >= 0 ? j : 0];   // unconditional load, selected below
+        bbar[p] = j >= 0 ? omega * vj : 0.0;
     });
 
     double A[NA];

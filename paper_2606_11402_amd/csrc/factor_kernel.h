@@ -121,19 +121,34 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
 // values with every other point, real or padded, are exactly 0, so it acts
 // as an identity row and column of K_cc without any masking in the
 // evaluation loops (the squared distances, >= 1e30, stay finite in float).
+// The loads are unconditional (a padded slot reads point 0) and the padding
+// is selected afterwards: a load under a condition cannot be issued early, so
+// the compiler would branch around each one and wait for it, one memory round
+// trip per row instead of two for all rows.
 template <typename T, typename TX, int K, int P>
 __device__ __forceinline__ void gather_rows(const TX* __restrict__ x, const int32_t* __restrict__ nbr, int64_t base,
                                             int r, T* c0, T* c1, T* c2, int* ok) {
     constexpr int R = K / P;
+    int32_t jv[R];
     static_for<0, R>([&](auto PI) {
         constexpr int p = PI;
-        const int32_t j = nbr[base + (int64_t)(p * P + r) * kTile];
-        ok[p] = j >= 0;
-        const int64_t jj = j >= 0 ? j : 0;
+        jv[p] = nbr[base + (int64_t)(p * P + r) * kTile];
+    });
+    TX x0[R], x1[R], x2[R];
+    static_for<0, R>([&](auto PI) {
+        constexpr int p = PI;
+        const int64_t jj = jv[p] >= 0 ? jv[p] : 0;
+        x0[p] = x[jj * 3 + 0];
+        x1[p] = x[jj * 3 + 1];
+        x2[p] = x[jj * 3 + 2];
+    });
+    static_for<0, R>([&](auto PI) {
+        constexpr int p = PI;
+        ok[p] = jv[p] >= 0;
         const T far = (T)(1e15 * (double)(p * P + r + 1));
-        c0[p] = j >= 0 ? (T)x[jj * 3 + 0] : far;
-        c1[p] = j >= 0 ? (T)x[jj * 3 + 1] : T(0);
-        c2[p] = j >= 0 ? (T)x[jj * 3 + 2] : T(0);
+        c0[p] = ok[p] ? (T)x0[p] : far;
+        c1[p] = ok[p] ? (T)x1[p] : T(0);
+        c2[p] = ok[p] ? (T)x2[p] : T(0);
     });
 }
 

@@ -339,19 +339,48 @@ void build_neighbours(vecchia_graph& g, int nthreads) {
 
 // Depths in slot order (the recurrence of Sec. 2.2), kept in rank space so
 // that the depths of a point's neighbours, its spatial neighbours, are read
-// from nearby memory.
-void build_depth(vecchia_graph& g) {
+// from nearby memory.  Slots are taken in blocks: the maximum over the
+// neighbours in earlier blocks is taken in parallel (their depths are final),
+// and only the rows that also have a neighbour inside the block (its depth
+// still -1) are finished sequentially, in slot order.  Far into the order
+// the neighbours of a point are spread over all preceding slots, so few rows
+// need the sequential step.
+void build_depth(vecchia_graph& g, int nthreads) {
     std::vector<int32_t> dr(g.n, 0);
+    for (int64_t i = g.n0; i < g.n; ++i) dr[g.rank_of[i]] = -1;
+    const int64_t block = 1 << 17;
+    std::vector<int32_t> dm(block);
+    std::vector<uint8_t> late(block);
     int32_t maxd = 0;
-    for (int64_t i = g.n0; i < g.n; ++i) {
-        const int32_t* row = &g.nbr[(size_t)(i - g.n0) * g.k];
-        int32_t dm = 0;
-        for (int m = 0; m < g.k; ++m) {
-            if (row[m] < 0) break;
-            dm = std::max(dm, dr[row[m]]);
+    for (int64_t a = g.n0; a < g.n; a += block) {
+        const int64_t b = std::min(a + block, g.n);
+        parallel_for(b - a, 2048, nthreads, [&](int64_t lo, int64_t hi) {
+            for (int64_t i = a + lo; i < a + hi; ++i) {
+                const int32_t* row = &g.nbr[(size_t)(i - g.n0) * g.k];
+                int32_t m = 0;
+                uint8_t l = 0;
+                for (int q = 0; q < g.k; ++q) {
+                    if (row[q] < 0) break;
+                    const int32_t d = dr[row[q]];
+                    l |= d < 0;
+                    m = std::max(m, d);
+                }
+                dm[i - a] = m;
+                late[i - a] = l;
+            }
+        });
+        for (int64_t i = a; i < b; ++i) {
+            int32_t m = dm[i - a];
+            if (late[i - a]) {
+                const int32_t* row = &g.nbr[(size_t)(i - g.n0) * g.k];
+                for (int q = 0; q < g.k; ++q) {
+                    if (row[q] < 0) break;
+                    m = std::max(m, dr[row[q]]);
+                }
+            }
+            dr[g.rank_of[i]] = m + 1;
+            maxd = std::max(maxd, m + 1);
         }
-        dr[g.rank_of[i]] = dm + 1;
-        maxd = std::max(maxd, dm + 1);
     }
     g.depth.resize(g.n);
     for (int64_t t = 0; t < g.n; ++t) g.depth[t] = dr[g.rank_of[t]];
@@ -411,7 +440,7 @@ extern "C" int graph_build(const double* x, int64_t n, int32_t d, int32_t k, int
         build_neighbours(*g, nthreads);
         g->times[1] = seconds_since(t0);
         t0 = std::chrono::steady_clock::now();
-        build_depth(*g);
+        build_depth(*g, nthreads);
         g->times[2] = seconds_since(t0);
         t0 = std::chrono::steady_clock::now();
         build_storage(*g);
