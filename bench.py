@@ -323,6 +323,7 @@ def main():
         out["k16_radial"] = k16_radial(args.steps, dev)
         if args.workload == 3 and args.k is None:
             out["k16_same_distribution"] = same_distribution_k16(w, n, args.steps, dev, args.threads)
+        out["adjoint_radial_2e22"] = adjoint_step(args.steps, dev)
     copy_gbs = copy_bandwidth(dev)
     out["copy_bandwidth_GBs"] = round(copy_gbs, 1)
     out["rooflines_other"]["forward+logdet"]["frac_of_copy"] = round(fl_gbs / copy_gbs, 4)
@@ -376,6 +377,43 @@ def same_distribution_k16(w, n, steps, dev, threads):
            "forward+logdet_GBs": round(gbs, 1), "forward+logdet_frac": round(gbs / HBM_PEAK_GBS, 4),
            "levels": g.n_levels}
     log("k16 same distribution:", res)
+    return res
+
+
+def adjoint_step(steps, dev):
+    """The gradient configuration (2^22 radial points, Matern-3/2, k = 16,
+    FP32 path): factor + forward + logdet, then the reverse sweep and the
+    theta kernel for loss = 1/2 |v - y|^2 / s^2 + logdet, s = 0.1."""
+    import torch
+    import workloads
+    from paper_2606_11402_amd import FP32, Factor, Graph, KernelParams
+    w = workloads.WORKLOADS[4]
+    g = Graph(w.points(w.n), w.k, w.n0)
+    dg = g.to_device(FP32, dev, with_children=True)
+    xi = torch.from_numpy(g.to_storage(w.xi(w.n))).float().to(dev)
+    y = torch.from_numpy(g.to_storage(w.data(w.n))).float().to(dev)
+    fac = Factor(dg, KernelParams(w.kind, w.sigma, w.ell, w.nugget))
+    v = torch.empty_like(xi)
+    scratch = None
+
+    def step():
+        nonlocal scratch
+        fac.refactor()
+        fac.forward(xi, out=v)
+        vbar = (v - y) / 0.01
+        _, _, theta = fac.backward(xi, v, v_bar=vbar, logdet_bar=1.0, scratch=scratch)
+        return theta
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        theta = step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    res = {"n": w.n, "k": w.k, "ms_per_step": round(ms, 3), "points_per_s": w.n / (ms * 1e-3),
+           "step": "factor + forward + reverse sweep + theta kernel", "theta_bar": [float(t) for t in theta.cpu()]}
+    log("adjoint:", res)
     return res
 
 
