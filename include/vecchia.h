@@ -238,7 +238,10 @@ typedef struct vecchia_serve_stats {
 /* arena: (device) 256-byte aligned buffer of arena_bytes owned by the caller
  * and not touched by it while the server lives (the HBM budget).  n_streams
  * in 1..64 (default priority), graph_workers host threads each running
- * graph_build with graph_threads threads.  mock != 0: no device calls at all
+ * graph_build; a request of n points builds with min(graph_threads,
+ * max(1, n / 2^16)) threads, so that small graphs start no threads and large
+ * ones (the tail of the latency) are built in parallel.  mock != 0: no
+ * device calls at all
  * (arena may be NULL); a running request completes after 3 serve_progress
  * calls and returns its input (host tests of the scheduler). */
 int serve_create(void* arena, size_t arena_bytes, int32_t n_streams, int32_t graph_workers, int32_t graph_threads,

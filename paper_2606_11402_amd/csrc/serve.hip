@@ -197,7 +197,8 @@ namespace {
 
 void build_request(vecchia_server* s, Request* r) {
     vecchia_graph* g = nullptr;
-    int rc = graph_build(r->x.data(), r->n, 3, r->k, r->n0, s->graph_threads, &g);
+    const int threads = (int)std::max<int64_t>(1, std::min<int64_t>(s->graph_threads, r->n >> 16));
+    int rc = graph_build(r->x.data(), r->n, 3, r->k, r->n0, threads, &g);
     if (rc == VECCHIA_OK) {
         graph_info(g, nullptr, nullptr, nullptr, nullptr, nullptr, &r->n_levels);
         r->order.resize(r->n);

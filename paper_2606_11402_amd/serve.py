@@ -28,7 +28,7 @@ class Server:
     """One engine over an HBM arena of ``budget`` bytes (a torch tensor the
     server keeps alive), or a host-only mock engine."""
 
-    def __init__(self, budget, n_streams=8, graph_workers=8, graph_threads=2, mock=False, device="cuda:0"):
+    def __init__(self, budget, n_streams=8, graph_workers=8, graph_threads=8, mock=False, device="cuda:0"):
         self._lib = _lib.load()
         self.mock = mock
         self.arena = None
