@@ -71,10 +71,12 @@ def apply_bytes_per_point(k, esz):
 
 
 def kernel_sources(precision_name, kp):
-    """Source files that define the factor kernel of this precision and width."""
+    """Source files that define the factor kernel of this precision and width,
+    and the graph builder that lays out its neighbour rows (their order sets
+    the kernel's gather pattern, hence its traffic)."""
     csrc = os.path.join(ROOT, "paper_2606_11402_amd", "csrc")
     return [os.path.join(csrc, f) for f in
-            ("common.h", "lanes.h", "factor_kernel.h", "factor_%s_k%d.hip" % (precision_name, kp))]
+            ("common.h", "lanes.h", "factor_kernel.h", "factor_%s_k%d.hip" % (precision_name, kp), "graph.cpp")]
 
 
 def source_digest(paths):
@@ -285,7 +287,6 @@ def main():
         "forward+logdet": {"bound": "hbm", "achieved": round(fl_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": round(fl_gbs / HBM_PEAK_GBS, 4), "ms": round(fwd_ms + ld_ms, 4),
                            "small_batch_runs_ms": round(prof.get("forward_run", (0.0, 0))[0] / steps, 4),
-                           "dataflow_ms": round(prof.get("forward_flow", (0.0, 0))[0] / steps, 4),
                            "per_batch_launches_ms": round(prof.get("forward_level", (0.0, 0))[0] / steps, 4)},
         "inverse_sparse": {"bound": "hbm", "achieved": round(inv_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": round(inv_gbs / HBM_PEAK_GBS, 4), "avg_launch_ms": round(inv_sparse_ms, 4)},
@@ -519,6 +520,7 @@ def sampled_check(g, fac, v, xi, kern, w, n, k, n0, samples=256):
     xs = g.points()                                    # FP64 values of the FP32 coordinates
     nb = g.nbr(0)[rows]
     b_gpu, s_gpu = fac.coefficient_rows(rows)
+    b_gpu = g.to_row_order(b_gpu, rows)                # device rows -> the rows of nbr(0)
     vh = v.double().cpu().numpy()
     xih = xi.double().cpu().numpy()
     ok_kern = oracle.Kernel(kern.kind, kern.sigma, kern.ell, kern.nugget)

@@ -107,8 +107,11 @@ int graph_export(const vecchia_graph* g, int32_t* order, int32_t* slot, int32_t*
 
 /* Neighbour indices in storage positions (host, caller-allocated):
  * layout 0 = row-major Ns x k, rows in sparse-index order, each row in
- * ascending (distance, slot); layout 1 = the tiled device layout (length
- * ceil(Ns/64) * kp * 64). */
+ * ascending (distance, slot), as Sec. 2.1 selects them; layout 1 = the tiled
+ * device layout (length ceil(Ns/64) * kp * 64), each row in ascending
+ * storage position with padding (-1) last: the same conditioning sets, in
+ * the order that keeps a wave's gathers on few cache lines.  Every device
+ * array indexed by a row position (b, the packed children) follows layout 1. */
 int graph_export_nbr(const vecchia_graph* g, int32_t layout, int32_t* nbr);
 
 /* Coordinates in storage order, 3 per point (zero padded for d < 3), as
@@ -117,7 +120,8 @@ int graph_export_points(const vecchia_graph* g, int32_t precision, void* xs);
 
 /* Children lists for the reverse sweep of the adjoint (host): for storage
  * position j, child[child_ptr[j] .. child_ptr[j+1]) are the packed entries
- * s' * kp + m of every sparse point s' whose m-th neighbour is j, ascending.
+ * s' * kp + m of every sparse point s' whose neighbour at position m of its
+ * layout-1 row is j, ascending.
  * child_ptr has N + 1 entries; child has Ns * k entries at most (the exact
  * count is child_ptr[N]).  EUNSUPPORTED if Ns * kp >= 2^31. */
 int graph_export_children(const vecchia_graph* g, int64_t* child_ptr, int32_t* child);

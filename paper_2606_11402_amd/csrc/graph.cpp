@@ -52,6 +52,7 @@ struct vecchia_graph {
     std::vector<int32_t> pos;          // slot -> storage
     std::vector<int32_t> pos_r;        // in-order rank -> storage
     std::vector<int32_t> level_ptr;    // n_levels + 2
+    int nthreads = 1;                  // host threads of the build, reused by the exports
     double times[4] = {0, 0, 0, 0};
 };
 
@@ -410,6 +411,21 @@ void build_storage(vecchia_graph& g) {
     for (int64_t r = 0; r < n; ++r) g.pos_r[r] = g.pos[g.seq[r]];
 }
 
+// Row of sparse point sp in the device order: storage positions ascending,
+// padding (-1) last.  The points of a tile are spatial neighbours inside one
+// batch, so with every row in this order the m-th gathers of a wave (of v in
+// the forward and inverse, of coordinates in the factor) fall on nearly the
+// same positions and touch few distinct cache lines; in distance order the
+// m-th nearest neighbours of adjacent points are scattered.  The conditioning
+// set, and with it every result up to rounding, does not depend on the order
+// of its members (b is permuted alike).
+void device_row(const vecchia_graph& g, int64_t sp, int32_t* out) {
+    const int32_t t = g.order[g.n0 + sp];
+    const int32_t* row = &g.nbr[(size_t)(t - g.n0) * g.k];
+    for (int m = 0; m < g.k; ++m) out[m] = row[m] >= 0 ? g.pos_r[row[m]] : -1;
+    std::sort(out, out + g.k, [](int32_t a, int32_t b) { return (uint32_t)a < (uint32_t)b; });
+}
+
 }  // namespace
 
 extern "C" int graph_build(const double* x, int64_t n, int32_t d, int32_t k, int32_t n0, int32_t n_threads,
@@ -433,6 +449,7 @@ extern "C" int graph_build(const double* x, int64_t n, int32_t d, int32_t k, int
         g->k = k;
         g->kp = vecchia_padded_k(k);
         g->n0 = n0;
+        g->nthreads = nthreads;
         auto t0 = std::chrono::steady_clock::now();
         build_tree(*g, x, nthreads);
         g->times[0] = seconds_since(t0);
@@ -492,18 +509,15 @@ extern "C" int graph_export_nbr(const vecchia_graph* g, int32_t layout, int32_t*
         return VECCHIA_OK;
     }
     const int64_t tiles = (ns + 63) / 64;
-    for (int64_t tile = 0; tile < tiles; ++tile)
-        for (int m = 0; m < kp; ++m)
+    parallel_for(tiles, 1024, g->nthreads, [&](int64_t a, int64_t b) {
+        int32_t row[VECCHIA_KMAX];
+        for (int64_t tile = a; tile < b; ++tile)
             for (int lane = 0; lane < 64; ++lane) {
                 const int64_t sp = tile * 64 + lane;
-                int32_t v = -1;
-                if (sp < ns && m < k) {
-                    const int32_t t = g->order[g->n0 + sp];
-                    const int32_t j = g->nbr[(size_t)(t - g->n0) * k + m];
-                    v = j >= 0 ? g->pos_r[j] : -1;
-                }
-                nbr[(tile * kp + m) * 64 + lane] = v;
+                if (sp < ns) device_row(*g, sp, row);
+                for (int m = 0; m < kp; ++m) nbr[(tile * kp + m) * 64 + lane] = (sp < ns && m < k) ? row[m] : -1;
             }
+    });
     return VECCHIA_OK;
 }
 
@@ -537,11 +551,11 @@ extern "C" int graph_export_children(const vecchia_graph* g, int64_t* child_ptr,
     }
     for (int64_t j = 0; j < g->n; ++j) cnt[j + 1] += cnt[j];
     std::memcpy(child_ptr, cnt.data(), sizeof(int64_t) * (g->n + 1));
+    int32_t row[VECCHIA_KMAX];
     for (int64_t sp = 0; sp < ns; ++sp) {
-        const int32_t t = g->order[g->n0 + sp];
-        const int32_t* row = &g->nbr[(size_t)(t - g->n0) * g->k];
+        device_row(*g, sp, row);                       // m: position in the device row
         for (int m = 0; m < g->k; ++m)
-            if (row[m] >= 0) child[cnt[g->pos_r[row[m]]]++] = (int32_t)(sp * g->kp + m);
+            if (row[m] >= 0) child[cnt[row[m]]++] = (int32_t)(sp * g->kp + m);
     }
     return VECCHIA_OK;
 }

@@ -89,6 +89,19 @@ class Graph:
         _lib.check(self._lib.graph_export_nbr(self._h, layout, _ptr(out)), "graph_export_nbr")
         return out[:size].reshape(self.ns, self.k) if layout == 0 else out[:size]
 
+    def to_row_order(self, b_dev, rows=None):
+        """Coefficients read from the device (``Factor.coefficients`` or
+        ``coefficient_rows``: one row per sparse point, in the device row
+        order, ascending storage position) reordered to the rows of
+        ``nbr(0)`` (ascending distance).  Host-side helper for comparisons
+        with a reference."""
+        nb = self.nbr(0) if rows is None else self.nbr(0)[np.asarray(rows)]
+        key = np.where(nb >= 0, nb.astype(np.int64), np.int64(1) << 40)
+        perm = np.argsort(key, axis=1, kind="stable")
+        out = np.zeros((nb.shape[0], self.k), dtype=np.asarray(b_dev).dtype)
+        np.put_along_axis(out, perm, np.asarray(b_dev)[:, :self.k], axis=1)
+        return out
+
     def points(self, precision=FP64):
         out = np.empty((self.n, 3), _NP_DTYPE[precision])
         _lib.check(self._lib.graph_export_points(self._h, precision, _ptr(out)), "graph_export_points")
@@ -201,7 +214,7 @@ class Factor:
     def forward(self, xi, out=None, per_batch=False):
         """v = F(xi), both in storage order.  per_batch=True passes the view
         without the device copy of level_ptr, so the library launches one
-        kernel per batch instead of its dataflow and small-batch kernels."""
+        kernel per batch instead of its one-workgroup runs of small batches."""
         xi = self._vec(xi, "xi")
         v = self._out(out)
         view = self.view

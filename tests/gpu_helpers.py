@@ -66,15 +66,17 @@ class Run:
         return out
 
     def coefficients_by_slot(self):
-        """(b rows, sigma) for sparse slots n0.. in slot order."""
+        """(b rows, sigma) for sparse slots n0.. in slot order, each b row in
+        the order of the graph's rows (ascending distance, as the oracle)."""
         b, s = self.fac.coefficients()
+        b = self.g.to_row_order(b)
         n0 = self.g.n0
         rows = self.g.slot[n0:] - n0
-        bo = np.empty((self.g.ns, self.g.kp))
+        bo = np.empty((self.g.ns, self.g.k))
         so = np.empty(self.g.ns)
         bo[rows] = b
         so[rows] = s
-        return bo[:, :self.g.k], so
+        return bo, so
 
 
 def oracle_run(x, k, n0, kern, xi_input=None):

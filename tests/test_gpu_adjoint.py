@@ -159,11 +159,12 @@ def test_workload4_loss_gradients(precision):
     # leaves in that state
     fac = gp.factor(w.sigma, w.ell)
     b_dev, s_dev = fac.coefficients()
+    b_dev = gr.to_row_order(b_dev)
     rows = gr.slot[128:] - 128
-    b_slot = np.empty((gr.ns, gr.kp))
+    b_slot = np.empty((gr.ns, gr.k))
     s_slot = np.empty(gr.ns)
     b_slot[rows], s_slot[rows] = b_dev, s_dev
-    state = oracle.Factor(of.L0, b_slot[:, :w.k], s_slot)
+    state = oracle.Factor(of.L0, b_slot, s_slot)
     v_dev = np.empty(n)
     v_dev[gr.slot] = v.detach().double().cpu().numpy()
     _, gth_state = oracle.forward_vjp(og, state, kern, xs, v_dev, (v_dev - ys) / s2, ld_bar=1.0)

@@ -97,7 +97,8 @@ def test_tiled_layout_matches_row_major():
     tl = g.nbr(1).reshape(g.ntiles, g.kp, 64)
     for sp in (0, 1, 63, 64, 500, g.ns - 1):
         row = tl[sp // 64, :, sp % 64]
-        assert row[:12].tolist() == rm[sp].tolist() and (row[12:] == -1).all()
+        # the device row holds the same neighbours, ascending storage position
+        assert row[:12].tolist() == sorted(rm[sp].tolist()) and (row[12:] == -1).all()
     assert (tl.reshape(g.ntiles, g.kp, 64)[-1, :, g.ns % 64:] == -1).all()
 
 
@@ -105,7 +106,7 @@ def test_children_lists_invert_neighbours():
     x = np.random.default_rng(9).random((800, 3))
     g = Graph(x, 8, 16)
     ptr, child = g.children()
-    nb = g.nbr(0)
+    nb = g.nbr(1).reshape(g.ntiles, g.kp, 64).transpose(0, 2, 1).reshape(-1, g.kp)[:g.ns]   # device rows
     seen = np.zeros_like(nb, dtype=bool)
     for j in range(g.n):
         entries = child[ptr[j]:ptr[j + 1]]
@@ -145,3 +146,19 @@ def test_storage_order_is_spatially_coherent_inside_levels():
         consecutive = np.linalg.norm(np.diff(xs[a:b], axis=0), axis=1).mean()
         rnd = np.linalg.norm(xs[a:b] - xs[np.random.default_rng(0).permutation(np.arange(a, b))], axis=1).mean()
         assert consecutive < 0.5 * rnd
+
+
+def test_row_order_helper_inverts_the_device_order():
+    # Graph.to_row_order maps values laid out along the device rows back to
+    # the rows of nbr(0); applied to the device rows' own indices it must
+    # give nbr(0) exactly (padded rows included)
+    for n, k, n0 in ((1000, 12, 41), (300, 32, 5)):
+        x = np.random.default_rng(n).random((n, 3))
+        g = Graph(x, k, n0)
+        dev = g.nbr(1).reshape(g.ntiles, g.kp, 64).transpose(0, 2, 1).reshape(-1, g.kp)[:g.ns]
+        back = g.to_row_order(dev.astype(np.int64))
+        rm = g.nbr(0)
+        pad = rm < 0
+        assert (back[~pad] == rm[~pad]).all() and (back[pad] == -1).all()
+        rows = np.array([0, 7, g.ns - 1])
+        assert (g.to_row_order(dev[rows].astype(np.int64), rows)[~pad[rows]] == rm[rows][~pad[rows]]).all()
