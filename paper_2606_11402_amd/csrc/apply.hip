@@ -10,7 +10,7 @@
 // reading entry m of their tiled rows as one contiguous 256-byte segment
 // (neighbour index and coefficient), then gathering v.  The forward
 // accumulates in the storage precision, the inverse in double.
-#include "common.h"
+#include "apply.h"
 #include "lanes.h"
 
 #include <type_traits>
@@ -51,19 +51,27 @@ __global__ __launch_bounds__(kBlock) void apply_kernel(const int32_t* __restrict
 }
 
 // A run of consecutive small batches [l_begin, l_end) in one workgroup: the
-// batches are processed in order with a workgroup barrier between them (the
-// barrier orders the global writes of batch l before the gathers of batch
-// l + 1 inside the workgroup), which replaces one launch per batch.  A
-// thread's first point of the next batch has its row (neighbour indices,
-// coefficients, sigma, xi: nothing that depends on v) loaded before the
-// barrier, so each batch costs one dependent memory round trip (the gather)
-// instead of two.
+// batches are processed in order with a workgroup barrier between them, which
+// replaces one launch per batch.  The values of storage positions [lo,
+// run_end) live in LDS for the whole run: positions [lo, run_start) are copied
+// in at the start (final values of earlier batches), the run's own outputs are
+// written there as well as to v, so a gather from a batch of the run reads
+// LDS after the barrier instead of making a round trip to L2; a gather below
+// lo reads its (final) value from v.  A thread's first point of the next
+// batch has its row (neighbour indices, coefficients, sigma, xi) loaded
+// before the barrier.  The dot product runs in the same order, on the same
+// values, as the per-batch kernel: the results are identical bit for bit.
 template <typename T, int KP>
-__global__ __launch_bounds__(kRunThreads) void forward_run_kernel(const int32_t* __restrict__ nbr,
+__global__ __launch_bounds__(run_threads(sizeof(T), KP)) void forward_run_kernel(const int32_t* __restrict__ nbr,
                                                                   const T* __restrict__ b, const T* __restrict__ sig,
                                                                   const T* __restrict__ xi, T* v, int n0,
                                                                   const int32_t* __restrict__ level_ptr, int l_begin,
-                                                                  int l_end) {
+                                                                  int l_end, int64_t lo) {
+    constexpr int NT = run_threads(sizeof(T), KP);
+    extern __shared__ unsigned char run_lds[];
+    T* vl = reinterpret_cast<T*>(run_lds);             // position p at vl[p - lo]
+    const int64_t run_start = level_ptr[l_begin];
+    for (int64_t p = lo + threadIdx.x; p < run_start; p += NT) vl[p - lo] = v[p];
     int32_t idx[KP];
     T w[KP];
     T sg = T(0), x = T(0);
@@ -82,17 +90,22 @@ __global__ __launch_bounds__(kRunThreads) void forward_run_kernel(const int32_t*
 #pragma unroll
         for (int m = 0; m < KP; ++m) {
             const int32_t j = idx[m];
-            const T vj = v[j >= 0 ? j : 0];
+            // one generic (flat) load from LDS or from v, whichever holds the value
+            const T* src = j >= lo ? vl + (j - lo) : v + (j >= 0 ? j : 0);
+            const T vj = *src;
             acc = fma(w[m], j >= 0 ? vj : T(0), acc);
         }
-        v[n0 + sp] = fma(sg, x, acc);
+        const T out = fma(sg, x, acc);
+        v[n0 + sp] = out;
+        vl[n0 + sp - lo] = out;
     };
-    int64_t s0 = (int64_t)level_ptr[l_begin] - n0, s1 = (int64_t)level_ptr[l_begin + 1] - n0;
+    int64_t s0 = run_start - n0, s1 = (int64_t)level_ptr[l_begin + 1] - n0;
     bool have = s0 + (int64_t)threadIdx.x < s1;
     if (have) load_row(s0 + threadIdx.x);
+    __syncthreads();                                   // the copied values are in LDS
     for (int l = l_begin; l < l_end; ++l) {
         if (have) finish_row(s0 + threadIdx.x);
-        for (int64_t sp = s0 + threadIdx.x + kRunThreads; sp < s1; sp += kRunThreads) {
+        for (int64_t sp = s0 + threadIdx.x + NT; sp < s1; sp += NT) {
             load_row(sp);
             finish_row(sp);
         }
@@ -111,23 +124,26 @@ __global__ __launch_bounds__(kRunThreads) void forward_run_kernel(const int32_t*
 
 template <typename T>
 static hipError_t launch_run_t(int kp, const int32_t* nbr, const void* b, const void* sig, const void* xi, void* v,
-                               int n0, const int32_t* level_ptr_dev, int l_begin, int l_end, hipStream_t s) {
+                               int n0, const int32_t* level_ptr_dev, int l_begin, int l_end, int64_t lo,
+                               int64_t run_end, hipStream_t s) {
     const T* bp = static_cast<const T*>(b);
     const T* sp = static_cast<const T*>(sig);
     const T* ip = static_cast<const T*>(xi);
     T* op = static_cast<T*>(v);
+    const size_t lds = (size_t)(run_end - lo) * sizeof(T);
+    if (lo < 0 || run_end <= lo || lds > (size_t)kRunLdsBytes) return hipErrorInvalidValue;
     switch (kp) {
         case 8:
-            hipLaunchKernelGGL((forward_run_kernel<T, 8>), dim3(1), dim3(kRunThreads), 0, s, nbr, bp, sp, ip, op, n0,
-                               level_ptr_dev, l_begin, l_end);
+            hipLaunchKernelGGL((forward_run_kernel<T, 8>), dim3(1), dim3(run_threads(sizeof(T), 8)), lds, s, nbr,
+                               bp, sp, ip, op, n0, level_ptr_dev, l_begin, l_end, lo);
             break;
         case 16:
-            hipLaunchKernelGGL((forward_run_kernel<T, 16>), dim3(1), dim3(kRunThreads), 0, s, nbr, bp, sp, ip, op, n0,
-                               level_ptr_dev, l_begin, l_end);
+            hipLaunchKernelGGL((forward_run_kernel<T, 16>), dim3(1), dim3(run_threads(sizeof(T), 16)), lds, s, nbr,
+                               bp, sp, ip, op, n0, level_ptr_dev, l_begin, l_end, lo);
             break;
         case 32:
-            hipLaunchKernelGGL((forward_run_kernel<T, 32>), dim3(1), dim3(kRunThreads), 0, s, nbr, bp, sp, ip, op, n0,
-                               level_ptr_dev, l_begin, l_end);
+            hipLaunchKernelGGL((forward_run_kernel<T, 32>), dim3(1), dim3(run_threads(sizeof(T), 32)), lds, s, nbr,
+                               bp, sp, ip, op, n0, level_ptr_dev, l_begin, l_end, lo);
             break;
         default:
             return hipErrorInvalidValue;
@@ -137,10 +153,10 @@ static hipError_t launch_run_t(int kp, const int32_t* nbr, const void* b, const 
 
 hipError_t launch_forward_run(int precision, int kp, const int32_t* nbr, const void* b, const void* sigma,
                               const void* xi, void* v, int n0, const int32_t* level_ptr_dev, int l_begin, int l_end,
-                              hipStream_t s) {
+                              int64_t lo, int64_t run_end, hipStream_t s) {
     if (precision == VECCHIA_FP32)
-        return launch_run_t<float>(kp, nbr, b, sigma, xi, v, n0, level_ptr_dev, l_begin, l_end, s);
-    return launch_run_t<double>(kp, nbr, b, sigma, xi, v, n0, level_ptr_dev, l_begin, l_end, s);
+        return launch_run_t<float>(kp, nbr, b, sigma, xi, v, n0, level_ptr_dev, l_begin, l_end, lo, run_end, s);
+    return launch_run_t<double>(kp, nbr, b, sigma, xi, v, n0, level_ptr_dev, l_begin, l_end, lo, run_end, s);
 }
 
 template <typename T, bool INVERSE>

@@ -6,7 +6,7 @@
 #include <string>
 #include <vector>
 
-#include "common.h"
+#include "apply.h"
 #include "status.h"
 
 using namespace vk;
@@ -192,16 +192,28 @@ extern "C" int vecchia_forward(const vecchia_view* view, const void* xi, void* v
     if (e != hipSuccess) return hip_fail(e, "vecchia_forward (dense block)");
     const int32_t* lp = view->level_ptr;
     const int L = view->n_levels;
+    const int64_t lds_cap = kRunLdsBytes / (view->precision == VECCHIA_FP32 ? 4 : 8);
     for (int l = 1; l <= L;) {
-        // a run of at least two consecutive small batches goes to one workgroup
+        // A run of at least two consecutive small batches goes to one
+        // workgroup.  Its LDS holds positions [lo, run_end): the whole prefix
+        // (lo = 0) while that fits, else the run's own positions (lo = its
+        // first position); the run stops before it would outgrow the LDS.
         int run_end = l;
-        if (view->level_ptr_dev)
-            while (run_end <= L && lp[run_end + 1] - lp[run_end] <= kRunMaxPoints) ++run_end;
+        if (view->level_ptr_dev) {
+            while (run_end <= L && lp[run_end + 1] - lp[run_end] <= kRunMaxPoints) {
+                const int64_t end_pos = lp[run_end + 1];
+                if (end_pos > lds_cap && end_pos - lp[l] > lds_cap) break;
+                ++run_end;
+            }
+        }
         if (run_end - l >= 2) {
             const int l0 = l;
+            const int64_t end_pos = lp[run_end];
+            const int64_t lo = end_pos <= lds_cap ? 0 : (int64_t)lp[l];
             e = timed("forward_run", s, [&] {
                 return launch_forward_run(view->precision, view->kp, view->nbr, ws<char>(view, lay.b),
-                                          ws<char>(view, lay.sigma), xi, v, view->n0, view->level_ptr_dev, l0, run_end, s);
+                                          ws<char>(view, lay.sigma), xi, v, view->n0, view->level_ptr_dev, l0, run_end,
+                                          lo, end_pos, s);
             });
             if (e != hipSuccess) return hip_fail(e, "vecchia_forward (run of small batches)");
             l = run_end;

@@ -166,17 +166,6 @@ constexpr int kStageProbe = 1, kStageMain = 2, kStageRedo = 4;   // FP32: sample
 hipError_t launch_factor_sparse(const FactorLaunch& a, hipStream_t stream);
 hipError_t launch_factor_dense(int precision, int kind, const void* x, int n0, const vecchia_kernel& kern,
                                double* l0, double* ld0, uint64_t* status, hipStream_t stream);
-hipError_t launch_forward_dense(int precision, const double* l0, int n0, const void* xi, void* v, hipStream_t stream);
-hipError_t launch_forward_level(int precision, int kp, const int32_t* nbr, const void* b, const void* sigma,
-                                const void* xi, void* v, int n0, int64_t s_begin, int64_t s_end, hipStream_t stream);
-constexpr int kRunThreads = 1024;        // workgroup of the small-batch runs
-constexpr int64_t kRunMaxPoints = 2048;  // a batch this small joins a run
-hipError_t launch_forward_run(int precision, int kp, const int32_t* nbr, const void* b, const void* sigma,
-                              const void* xi, void* v, int n0, const int32_t* level_ptr_dev, int l_begin, int l_end,
-                              hipStream_t stream);
-hipError_t launch_inverse_dense(int precision, const double* l0, int n0, const void* v, void* xi, hipStream_t stream);
-hipError_t launch_inverse_sparse(int precision, int kp, const int32_t* nbr, const void* b, const void* sigma,
-                                 const void* v, void* xi, int n0, int64_t ns, hipStream_t stream);
 struct BackwardLaunch {
     int precision, kp, n0, n_levels;
     int64_t n, ns;

@@ -3,7 +3,7 @@
 // K[0:n0, 0:n0], always in double.  n0 <= 128, so the whole block sits in
 // one workgroup's LDS (n0 x (n0+1) doubles, 132 KB of gfx950's 160 KB); the
 // factor is written to the workspace as L0 (row-major, zero upper part).
-#include "common.h"
+#include "apply.h"
 
 namespace vk {
 

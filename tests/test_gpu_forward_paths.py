@@ -1,9 +1,12 @@
 """The forward as the library runs it (one workgroup per run of small
-batches, one launch per larger batch) against the forward with one launch per
-batch for every batch.  Both evaluate every v_i with the same operations in
-the same order, so they must agree bit for bit; the per-batch forward is
-itself checked against the oracle in test_gpu_parity.py.  Sizes are chosen so
-that both kinds of batches occur."""
+batches, with the run's values in LDS; one launch per larger batch) against
+the forward with one launch per batch for every batch.  Both evaluate every
+v_i with the same operations in the same order, so they must agree bit for
+bit; the per-batch forward is itself checked against the oracle in
+test_gpu_parity.py.  Sizes are chosen so that both kinds of batches occur and
+that runs outgrow the LDS copy (runs whose LDS starts at position 0 and runs
+whose LDS starts at their own first position, reading earlier values from
+HBM); FP64 at k = 32 runs with the half-size workgroup."""
 import numpy as np
 import pytest
 import torch
@@ -17,7 +20,7 @@ SMALL_BATCH = 2048   # batches up to this size go to the one-workgroup run kerne
 
 
 @pytest.mark.parametrize("wl,n,k,precision", [(3, 1 << 21, 32, FP32), (2, 1 << 20, 16, FP32),
-                                              (1, 1 << 19, 8, FP64)])
+                                              (1, 1 << 19, 8, FP64), (3, 1 << 21, 32, FP64)])
 def test_forward_paths_match_per_batch(wl, n, k, precision):
     w = workloads.WORKLOADS[wl]
     print("forward paths: workload", wl, "n", n, "k", k, "precision", precision, flush=True)
