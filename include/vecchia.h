@@ -178,7 +178,7 @@ int vecchia_factor(vecchia_view* view, const vecchia_kernel* kern, void* stream)
  * v_i = b_i . v[c(i)] + sigma_i xi_i.  xi and v are device arrays of N
  * elements (double or float per view->precision) in storage order; they must
  * not overlap.  One launch per batch; with view->level_ptr_dev set, runs of
- * consecutive small batches (<= 2048 points) go to one workgroup each, with a
+ * consecutive small batches (<= 512 points) go to one workgroup each, with a
  * workgroup barrier between batches. */
 int vecchia_forward(const vecchia_view* view, const void* xi, void* v, void* stream);
 

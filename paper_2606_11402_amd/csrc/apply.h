@@ -16,7 +16,7 @@ constexpr int kRunThreads = 1024;        // workgroup of the small-batch runs
 __host__ __device__ constexpr int run_threads(int elem_bytes, int kp) {
     return elem_bytes == 8 && kp == 32 ? kRunThreads / 2 : kRunThreads;
 }
-constexpr int64_t kRunMaxPoints = 2048;  // a batch this small joins a run
+constexpr int64_t kRunMaxPoints = 512;   // a batch this small joins a run
 constexpr int64_t kRunLdsBytes = 65536;  // LDS copy of the positions [lo, run_end) a run reads and writes
 // One workgroup over batches [l_begin, l_end); LDS holds positions [lo, run_end)
 // (lo = 0 or the run's first position, (run_end - lo) * element size <= kRunLdsBytes).

@@ -16,7 +16,7 @@ from paper_2606_11402_amd import FP32, FP64, Factor, Graph, KernelParams
 
 pytestmark = pytest.mark.gpu
 
-SMALL_BATCH = 2048   # batches up to this size go to the one-workgroup run kernel
+SMALL_BATCH = 512    # batches up to this size go to the one-workgroup run kernel
 
 
 @pytest.mark.parametrize("wl,n,k,precision", [(3, 1 << 21, 32, FP32), (2, 1 << 20, 16, FP32),
