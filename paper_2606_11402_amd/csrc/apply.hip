@@ -131,7 +131,7 @@ static hipError_t launch_run_t(int kp, const int32_t* nbr, const void* b, const 
     const T* ip = static_cast<const T*>(xi);
     T* op = static_cast<T*>(v);
     const size_t lds = (size_t)(run_end - lo) * sizeof(T);
-    if (lo < 0 || run_end <= lo || lds > (size_t)kRunLdsBytes) return hipErrorInvalidValue;
+    if (lo < 0 || run_end < lo || lds > (size_t)kRunLdsBytes) return hipErrorInvalidValue;   // a run of empty batches has no LDS
     switch (kp) {
         case 8:
             hipLaunchKernelGGL((forward_run_kernel<T, 8>), dim3(1), dim3(run_threads(sizeof(T), 8)), lds, s, nbr,

@@ -40,22 +40,24 @@ def test_forward_paths_match_per_batch(wl, n, k, precision):
         assert ((xi_back - xi).abs().max() / xi.abs().max()).item() < 1e-10
 
 
-def test_forward_with_empty_batches_in_view():
-    """An empty batch in level_ptr (allowed by the view) changes nothing."""
+@pytest.mark.parametrize("repeats", [1, 2])
+def test_forward_with_empty_batches_in_view(repeats):
+    """Empty batches in level_ptr (allowed by the view) change nothing: one
+    alone, or two in a row (a run made of empty batches only, no LDS)."""
     w = workloads.WORKLOADS[2]
     n, k = 1 << 19, 16
     g = Graph(w.points(n), k, w.n0)
     lp = np.asarray(g.level_ptr).copy()
     sizes = np.diff(lp[1:])
     big = int(np.argmax(sizes)) + 1       # level index of the largest batch
-    # repeat one boundary: batch `big` becomes empty, the following one takes its points
-    lp2 = np.concatenate([lp[:big + 1], lp[big:]]).astype(np.int32)
+    # repeat one boundary: `repeats` empty batches, the following one takes the points of `big`
+    lp2 = np.concatenate([lp[:big + 1]] + [lp[big:big + 1]] * (repeats - 1) + [lp[big:]]).astype(np.int32)
     dg = g.to_device(FP32, "cuda:0")
     fac = Factor(dg, KernelParams(w.kind, w.sigma, w.ell, w.nugget))
     xi = torch.from_numpy(g.to_storage(w.xi(n))).float().cuda()
     v_ref = fac.forward(xi, per_batch=True)
     fac.view.level_ptr = lp2.ctypes.data
-    fac.view.n_levels = dg.n_levels + 1
+    fac.view.n_levels = dg.n_levels + repeats
     lp_dev = torch.from_numpy(lp2).cuda()
     fac.view.level_ptr_dev = lp_dev.data_ptr()
     v = fac.forward(xi)
