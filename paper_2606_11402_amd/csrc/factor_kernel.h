@@ -63,7 +63,7 @@ struct FactorArgs {
 // these conditional variances, and the float pass would be wasted work), the
 // float pass is skipped and every point is computed in double.  The choice
 // depends only on the inputs, so results stay reproducible.
-constexpr int64_t kProbeStride = 64;
+constexpr int64_t kProbeStride = 256;
 __device__ __forceinline__ bool all_points_in_double(const uint64_t* status) {
     const uint64_t flagged = status[5], sampled = status[6];
     return sampled > 0 && 4 * flagged > 3 * sampled;
