@@ -7,18 +7,25 @@
 
 namespace vk {
 
-constexpr int kDenseThreads = VECCHIA_N0MAX;   // one thread per row
+constexpr int kDenseThreads = VECCHIA_N0MAX;   // one thread per row (dense forward / inverse)
 constexpr int kLd = VECCHIA_N0MAX + 1;        // padded LDS row stride
+constexpr int kDenseCols = 8;                 // factor: threads per row, each on every 8th column
+constexpr int kDenseFactorThreads = VECCHIA_N0MAX * kDenseCols;
 
+// Right-looking Cholesky in LDS.  Thread (i, c) owns the columns c, c + 8,
+// ... of row i, so the rank-1 update of step j spreads row i's (i - j)
+// entries over 8 threads; every entry still receives its updates one step
+// after the other, in the same order as with one thread per row.
 template <typename TX, int KIND>
-__global__ __launch_bounds__(kDenseThreads) void factor_dense_kernel(const TX* __restrict__ x, int n0,
-                                                                       Cov<double> cov, double nugget,
-                                                                       double* __restrict__ l0,
-                                                                       double* __restrict__ ld0,
-                                                                       uint64_t* __restrict__ status) {
+__global__ __launch_bounds__(kDenseFactorThreads) void factor_dense_kernel(const TX* __restrict__ x, int n0,
+                                                                             Cov<double> cov, double nugget,
+                                                                             double* __restrict__ l0,
+                                                                             double* __restrict__ ld0,
+                                                                             uint64_t* __restrict__ status) {
     __shared__ double A[VECCHIA_N0MAX * kLd];
-    const int i = threadIdx.x;
-    if (i == 0) {
+    const int tid = threadIdx.x;
+    const int i = tid / kDenseCols, c = tid % kDenseCols;
+    if (tid == 0) {
         status[0] = kStatusNone;   // first failing storage position
         status[1] = 0;             // failing points
         status[2] = 0;             // FP32 path: points recomputed in double
@@ -29,7 +36,7 @@ __global__ __launch_bounds__(kDenseThreads) void factor_dense_kernel(const TX* _
     }
     if (i < n0) {
         const double a0 = (double)x[i * 3 + 0], a1 = (double)x[i * 3 + 1], a2 = (double)x[i * 3 + 2];
-        for (int l = 0; l <= i; ++l) {
+        for (int l = c; l <= i; l += kDenseCols) {
             const double r2 = sqdist3(a0, a1, a2, (double)x[l * 3 + 0], (double)x[l * 3 + 1], (double)x[l * 3 + 2]);
             A[i * kLd + l] = cov_r2<KIND>(r2, cov) + (l == i ? nugget : 0.0);
         }
@@ -43,18 +50,20 @@ __global__ __launch_bounds__(kDenseThreads) void factor_dense_kernel(const TX* _
         if (!(d > 0.0) && bad_row < 0) bad_row = j;
         lsum += log(sq);
         __syncthreads();
-        if (i == j) A[j * kLd + j] = sq;
-        if (i > j && i < n0) A[i * kLd + j] = A[i * kLd + j] / sq;
+        if (c == 0) {
+            if (i == j) A[j * kLd + j] = sq;
+            if (i > j && i < n0) A[i * kLd + j] = A[i * kLd + j] / sq;
+        }
         __syncthreads();
         if (i > j && i < n0) {
             const double lij = A[i * kLd + j];
-            for (int l = j + 1; l <= i; ++l) A[i * kLd + l] = fma(-lij, A[l * kLd + j], A[i * kLd + l]);
+            for (int l = j + 1 + c; l <= i; l += kDenseCols) A[i * kLd + l] = fma(-lij, A[l * kLd + j], A[i * kLd + l]);
         }
         __syncthreads();
     }
     if (i < n0)
-        for (int l = 0; l < n0; ++l) l0[i * n0 + l] = l <= i ? A[i * kLd + l] : 0.0;
-    if (i == 0) {
+        for (int l = c; l < n0; l += kDenseCols) l0[i * n0 + l] = l <= i ? A[i * kLd + l] : 0.0;
+    if (tid == 0) {
         *ld0 = lsum;
         if (bad_row >= 0) {
             status[0] = (uint64_t)bad_row;
@@ -100,15 +109,15 @@ static hipError_t launch_factor_dense_t(int kind, const void* x, int n0, const v
     const TX* xp = static_cast<const TX*>(x);
     switch (kind) {
         case 0:
-            hipLaunchKernelGGL((factor_dense_kernel<TX, 0>), dim3(1), dim3(kDenseThreads), 0, s, xp, n0, cov,
+            hipLaunchKernelGGL((factor_dense_kernel<TX, 0>), dim3(1), dim3(kDenseFactorThreads), 0, s, xp, n0, cov,
                                kern.nugget, l0, ld0, status);
             break;
         case 1:
-            hipLaunchKernelGGL((factor_dense_kernel<TX, 1>), dim3(1), dim3(kDenseThreads), 0, s, xp, n0, cov,
+            hipLaunchKernelGGL((factor_dense_kernel<TX, 1>), dim3(1), dim3(kDenseFactorThreads), 0, s, xp, n0, cov,
                                kern.nugget, l0, ld0, status);
             break;
         case 2:
-            hipLaunchKernelGGL((factor_dense_kernel<TX, 2>), dim3(1), dim3(kDenseThreads), 0, s, xp, n0, cov,
+            hipLaunchKernelGGL((factor_dense_kernel<TX, 2>), dim3(1), dim3(kDenseFactorThreads), 0, s, xp, n0, cov,
                                kern.nugget, l0, ld0, status);
             break;
         default:
