@@ -144,7 +144,7 @@ typedef struct vecchia_view {
     int32_t precision;         /* VECCHIA_FP64 or VECCHIA_FP32 */
     int32_t redo_log2;         /* VECCHIA_FP32: a point whose smallest Cholesky pivot is below
                                   2^-redo_log2 * K_ii, or not positive, is recomputed entirely in
-                                  double (results stored as float).  0 = default (16); < 0 = only
+                                  double (results stored as float).  0 = default (8); < 0 = only
                                   points whose float factorisation fails.  Ignored for FP64. */
     const void* x;             /* (device) N x 3 coordinates in storage order, double or float */
     const int32_t* nbr;        /* (device) tiled neighbour indices (graph_export_nbr layout 1) */

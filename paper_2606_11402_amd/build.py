@@ -56,13 +56,27 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
 
 
-def build(jobs=None, verbose=False):
-    """Compile every source and link ``libvecchia.so``; always recompiles."""
+def _up_to_date(src):
+    """An object is current when it is newer than its source and than every
+    header it may include (all of csrc/*.h and include/*.h)."""
+    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    if not os.path.exists(obj):
+        return False
+    deps = [src] + glob.glob(os.path.join(CSRC, "*.h")) + glob.glob(os.path.join(INCLUDE, "*.h"))
+    return os.path.getmtime(obj) > max(os.path.getmtime(d) for d in deps)
+
+
+def build(jobs=None, verbose=False, incremental=False):
+    """Compile every source and link ``libvecchia.so``.  By default every
+    source is recompiled; incremental=True recompiles only the objects older
+    than their source or a header."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = sources()
     jobs = jobs or min(16, os.cpu_count() or 4)
+    todo = [s for s in srcs if not (incremental and _up_to_date(s))]
     with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        list(ex.map(_compile, todo))
+    objs = [os.path.join(BUILD, os.path.basename(s) + ".o") for s in srcs]
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs + ["-pthread"])
     os.replace(tmp, LIB)
@@ -72,5 +86,5 @@ def build(jobs=None, verbose=False):
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, incremental="--incremental" in sys.argv[1:])
     sys.exit(0)

@@ -30,8 +30,11 @@ __global__ __launch_bounds__(kBlock) void apply_kernel(const int32_t* __restrict
     // The inverse subtracts two nearly equal numbers (v_i and its conditional
     // mean) and divides by a possibly small sigma_i, so it accumulates in
     // double; double FMA runs at the FP32 rate on CDNA4 and this kernel is
-    // bound by HBM, so the wider accumulator is free.  The forward sum has no
-    // cancellation and accumulates in the storage precision.
+    // bound by HBM, so the wider accumulator is free.  The forward sum can
+    // cancel too (sum |b_m v_m| reaches ~7 max|v| on the radial Matern cloud)
+    // but its result is not divided by sigma_i: with float coefficients and
+    // values, float accumulation adds ~4e-7 of max|v| there (CPU emulation),
+    // so it accumulates in the storage precision, as the float path specifies.
     using Acc = typename std::conditional<INVERSE, double, T>::type;
     const T* vsrc = INVERSE ? in : out;
     Acc acc = Acc(0);
@@ -238,13 +241,17 @@ __device__ Neumaier block_reduce(Neumaier acc, double* S, double* C) {
 
 // Stage 1: workgroup g sums a contiguous slice of the per-block partials
 // (fixed slices, fixed order: the result does not depend on scheduling).
-__global__ __launch_bounds__(kLdThreads) void logdet_partial_kernel(const double* __restrict__ part, int64_t n,
+__global__ __launch_bounds__(kLdThreads) void logdet_partial_kernel(const double* __restrict__ part,
+                                                                    const long long* __restrict__ fix, int64_t n,
                                                                     double* __restrict__ stage) {
     __shared__ double S[kLdThreads], C[kLdThreads];
     const int64_t per = (n + gridDim.x - 1) / gridDim.x;
     const int64_t lo = (int64_t)blockIdx.x * per, hi = lo + per < n ? lo + per : n;
     Neumaier acc;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += kLdThreads) acc.add(part[i]);
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kLdThreads) {
+        acc.add(part[i]);
+        acc.add((double)fix[i] * (1.0 / 4294967296.0));   // recomputed points of the block, 2^-32 fixed point
+    }
     const Neumaier tot = block_reduce(acc, S, C);
     if (threadIdx.x == 0) {
         stage[2 * blockIdx.x] = tot.s;
@@ -252,10 +259,9 @@ __global__ __launch_bounds__(kLdThreads) void logdet_partial_kernel(const double
     }
 }
 
-// Stage 2: the stage-1 pairs, the dense block and the recomputed points.
+// Stage 2: the stage-1 pairs and the dense block.
 __global__ __launch_bounds__(kLdThreads) void logdet_final_kernel(const double* __restrict__ stage, int nstage,
                                                                   const double* __restrict__ ld0,
-                                                                  const uint64_t* __restrict__ status,
                                                                   double* __restrict__ out) {
     __shared__ double S[kLdThreads], C[kLdThreads];
     Neumaier acc;
@@ -263,17 +269,16 @@ __global__ __launch_bounds__(kLdThreads) void logdet_final_kernel(const double* 
     Neumaier a = block_reduce(acc, S, C);
     if (threadIdx.x == 0) {
         a.add(*ld0);
-        a.add((double)(long long)status[3] / 4294967296.0);   // recomputed points, fixed point 2^-32
         out[0] = 2.0 * (a.s + a.c);
     }
 }
 
-hipError_t launch_logdet(const double* ldpart, int64_t nparts, const double* ld0, const uint64_t* status,
+hipError_t launch_logdet(const double* ldpart, const long long* ldfix, int64_t nparts, const double* ld0,
                          double* stage, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(logdet_partial_kernel, dim3(kLdBlocks), dim3(kLdThreads), 0, s, ldpart, nparts, stage);
+    hipLaunchKernelGGL(logdet_partial_kernel, dim3(kLdBlocks), dim3(kLdThreads), 0, s, ldpart, ldfix, nparts, stage);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(logdet_final_kernel, dim3(1), dim3(kLdThreads), 0, s, stage, kLdBlocks, ld0, status, out);
+    hipLaunchKernelGGL(logdet_final_kernel, dim3(1), dim3(kLdThreads), 0, s, stage, kLdBlocks, ld0, out);
     return hipGetLastError();
 }
 

@@ -12,8 +12,11 @@
 using namespace vk;
 
 // FP32 path: a point is recomputed in double when one of its pivots falls
-// below 2^-kDefaultRedoLog2 * K_ii (view->redo_log2 == 0).
-constexpr int kDefaultRedoLog2 = 16;
+// below 2^-kDefaultRedoLog2 * K_ii (view->redo_log2 == 0).  Emulated on the
+// CPU (exact solves of float-rounded K_cc on the radial Matern and clumped
+// squared-exponential clouds), the points kept in float below 2^-8 move the
+// forward result by up to ~1e-5 of max|v|; at 2^-16 by up to ~1e-3.
+constexpr int kDefaultRedoLog2 = 8;
 
 namespace {
 
@@ -83,7 +86,9 @@ int check_kernel(const vecchia_kernel* k) {
 int check_view(const vecchia_view* v, Layout* lay, const char* who) {
     if (!v) return vecchia_set_error(VECCHIA_EINVAL, "%s: view is NULL", who);
     if (v->n < 1 || v->n >= (int64_t(1) << 31)) return vecchia_set_error(VECCHIA_EINVAL, "%s: need 1 <= N < 2^31", who);
-    if (v->k < 1 || v->k > VECCHIA_KMAX) return vecchia_set_error(VECCHIA_EINVAL, "%s: need 1 <= k <= %d", who, VECCHIA_KMAX);
+    if (v->k < 1) return vecchia_set_error(VECCHIA_EINVAL, "%s: need k >= 1", who);
+    if (v->k > VECCHIA_KMAX)
+        return vecchia_set_error(VECCHIA_EUNSUPPORTED, "%s: k=%d exceeds the compiled maximum %d", who, v->k, VECCHIA_KMAX);
     if (v->kp != vecchia_padded_k(v->k))
         return vecchia_set_error(VECCHIA_EINVAL, "%s: kp=%d does not match k=%d (expected %d)", who, v->kp, v->k,
                                  vecchia_padded_k(v->k));
@@ -117,8 +122,11 @@ T* ws(const vecchia_view* v, size_t off) {
 
 extern "C" int vecchia_workspace_bytes(int64_t n, int32_t k, int32_t n0, int32_t precision, size_t* bytes) {
     if (!bytes) return vecchia_set_error(VECCHIA_EINVAL, "vecchia_workspace_bytes: bytes is NULL");
+    if (k < 1) return vecchia_set_error(VECCHIA_EINVAL, "vecchia_workspace_bytes: need k >= 1");
+    if (k > VECCHIA_KMAX)
+        return vecchia_set_error(VECCHIA_EUNSUPPORTED, "vecchia_workspace_bytes: k=%d exceeds the compiled maximum %d", k,
+                                 VECCHIA_KMAX);
     const int kp = vecchia_padded_k(k);
-    if (kp < 0) return vecchia_set_error(VECCHIA_EINVAL, "vecchia_workspace_bytes: k=%d out of range", k);
     if (n < 1 || n0 < 1 || n0 > n) return vecchia_set_error(VECCHIA_EINVAL, "vecchia_workspace_bytes: need 1 <= n0 <= N");
     if (precision != VECCHIA_FP64 && precision != VECCHIA_FP32)
         return vecchia_set_error(VECCHIA_EINVAL, "vecchia_workspace_bytes: bad precision");
@@ -151,6 +159,7 @@ extern "C" int vecchia_factor(vecchia_view* view, const vecchia_kernel* kern, vo
     a.b = ws<char>(view, lay.b);
     a.sigma = ws<char>(view, lay.sigma);
     a.ldpart = ws<double>(view, lay.ldpart);
+    a.ldfix = ws<long long>(view, lay.ldfix);
     a.status = ws<uint64_t>(view, lay.status);
     a.redo = ws<uint32_t>(view, lay.redo);
     {
@@ -258,8 +267,8 @@ extern "C" int vecchia_logdet(const vecchia_view* view, double* out, void* strea
     if (!out) return vecchia_set_error(VECCHIA_EINVAL, "vecchia_logdet: out is NULL");
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = timed("logdet", s, [&] {
-        return launch_logdet(ws<double>(view, lay.ldpart), lay.ns > 0 ? lay.nparts : 0, ws<double>(view, lay.ld0),
-                             ws<uint64_t>(view, lay.status), ws<double>(view, lay.ldstage), out, s);
+        return launch_logdet(ws<double>(view, lay.ldpart), ws<long long>(view, lay.ldfix), lay.ns > 0 ? lay.nparts : 0,
+                             ws<double>(view, lay.ld0), ws<double>(view, lay.ldstage), out, s);
     });
     if (e != hipSuccess) return hip_fail(e, "vecchia_logdet");
     return VECCHIA_OK;

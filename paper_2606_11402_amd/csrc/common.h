@@ -35,7 +35,7 @@ __host__ __device__ constexpr int factor_min_waves(int elem_bytes, int kp) {
 struct Layout {
     int64_t ns = 0, ntiles = 0, nparts = 0;
     size_t esz = 0;
-    size_t b = 0, sigma = 0, l0 = 0, ldpart = 0, ld0 = 0, ldstage = 0, status = 0, redo = 0, total = 0;
+    size_t b = 0, sigma = 0, l0 = 0, ldpart = 0, ldfix = 0, ld0 = 0, ldstage = 0, status = 0, redo = 0, total = 0;
 };
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -56,6 +56,8 @@ inline Layout workspace_layout(int64_t n, int kp, int n0, int precision) {
     off = align256(off + (size_t)n0 * n0 * sizeof(double));
     w.ldpart = off;
     off = align256(off + (size_t)(w.nparts > 0 ? w.nparts : 1) * sizeof(double));
+    w.ldfix = off;
+    off = align256(off + (size_t)(w.nparts > 0 ? w.nparts : 1) * sizeof(int64_t));
     w.ld0 = off;
     off = align256(off + sizeof(double));
     w.ldstage = off;
@@ -156,6 +158,7 @@ struct FactorLaunch {
     void* b;
     void* sigma;
     double* ldpart;
+    long long* ldfix;
     uint64_t* status;
     uint32_t* redo;
     double redo_ratio;
@@ -208,6 +211,7 @@ inline BackwardScratch backward_scratch(int64_t n, int kp, int n0, int precision
 }
 
 constexpr int kLogdetStage = 256;   // first-stage workgroups of the logdet reduction
-hipError_t launch_logdet(const double* ldpart, int64_t nparts, const double* ld0, const uint64_t* status,
+// log det = 2 (sum_i (ldpart[i] + 2^-32 ldfix[i]) + ld0), compensated, fixed order.
+hipError_t launch_logdet(const double* ldpart, const long long* ldfix, int64_t nparts, const double* ld0,
                          double* stage, double* out, hipStream_t stream);
 }  // namespace vk

@@ -29,7 +29,7 @@ __global__ __launch_bounds__(kDenseFactorThreads) void factor_dense_kernel(const
         status[0] = kStatusNone;   // first failing storage position
         status[1] = 0;             // failing points
         status[2] = 0;             // FP32 path: points recomputed in double
-        status[3] = 0;             // their sum of log sigma, fixed point
+        status[3] = 0;             // unused
         status[4] = 0;             // unused
         status[5] = 0;             // FP32 policy sample: points that would be recomputed in double
         status[6] = 0;             // FP32 policy sample: points looked at

@@ -44,8 +44,9 @@ struct FactorArgs {
     T* b;                  // tiled coefficients
     T* sigma;              // conditional standard deviation per sparse index
     double* ldpart;        // per-block sum of log sigma
-    uint64_t* status;      // [first bad position, bad count, redo count, redo log-sigma sum (fixed point),
-                           //  unused, policy sample: flagged, looked at]
+    long long* ldfix;      // per-block sum of log sigma of the points recomputed from the list, 2^-32 fixed point
+    uint64_t* status;      // [first bad position, bad count, redo count, unused, unused,
+                           //  policy sample: flagged, looked at]
     uint32_t* redo;        // FP32 path: sparse indices recomputed in double
     int64_t ns;
     int64_t nblocks;
@@ -59,18 +60,27 @@ struct FactorArgs {
 // FP32 path, precision policy.  A sample pass runs the float factor on every
 // kProbeStride-th block and counts, in status[5] and status[6], the points
 // it would send to the double recompute and the points it looked at.  When
-// more than three quarters would go (kernel values in float cannot resolve
-// these conditional variances, and the float pass would be wasted work), the
-// float pass is skipped and every point is computed in double.  The choice
-// depends only on the inputs, so results stay reproducible.
+// more than a width-dependent fraction would go, the float pass is skipped
+// and every point is computed in double, in storage order.  The fraction is
+// where the float pass stops paying for itself: a double recompute driven by
+// the list costs about twice the per-point time of the double pass in storage
+// order (scattered points), and the float pass with its refinement costs
+// nearly as much as the double pass at k <= 16 (double FMA runs at the float
+// rate on CDNA4; only the exponentials and square roots are cheaper in
+// float), about two thirds of it at k = 32.  The choice depends only on the
+// inputs, so results stay reproducible.
 constexpr int64_t kProbeStride = 256;
+template <int K>
 __device__ __forceinline__ bool all_points_in_double(const uint64_t* status) {
     const uint64_t flagged = status[5], sampled = status[6];
-    return sampled > 0 && 4 * flagged > 3 * sampled;
+    constexpr uint64_t inv_frac = K <= 16 ? 16 : 8;   // 1/16 of the points at k <= 16, 1/8 above
+    return sampled > 0 && inv_frac * flagged > sampled;
 }
 
-// Fixed-point scale of the log-sigma sum of recomputed points: integer
-// additions commute, so the sum does not depend on the order of the atomics.
+// Fixed-point scale of the log-sigma sums of recomputed points: integer
+// additions commute, so a block's sum does not depend on the order of the
+// atomics.  A block holds at most kBlock points and |log sigma| < 745 for any
+// positive double variance, so a block's sum stays below 2^50 (no overflow).
 constexpr double kFixScale = 4294967296.0;  // 2^32
 
 template <int P>
@@ -399,8 +409,11 @@ __global__ __launch_bounds__(kBlock, factor_min_waves(sizeof(T), K)) void factor
     const int r = tid % P;
     constexpr bool probe = REFINE && PROBE;
     const int64_t blk = probe ? (int64_t)blockIdx.x * a.probe_stride : xcd_block(blockIdx.x, a.nblocks);
-    if (REFINE && !probe && all_points_in_double(a.status)) {
-        if (tid == 0) a.ldpart[blk] = 0.0;            // every point goes to factor_redo_kernel
+    if (REFINE && !probe && all_points_in_double<K>(a.status)) {
+        if (tid == 0) {                                // every point goes to factor_redo_kernel
+            a.ldpart[blk] = 0.0;
+            a.ldfix[blk] = 0;
+        }
         return;
     }
     const int64_t sp_raw = blk * PTS + tid / P;
@@ -474,6 +487,7 @@ __global__ __launch_bounds__(kBlock, factor_min_waves(sizeof(T), K)) void factor
         double s = 0.0;
         for (int w = 0; w < kBlock / 64; ++w) s += part[w];
         a.ldpart[blk] = s;
+        a.ldfix[blk] = 0;                              // factor_redo_kernel adds the deferred points
     }
 }
 
@@ -481,25 +495,26 @@ __global__ __launch_bounds__(kBlock, factor_min_waves(sizeof(T), K)) void factor
 // Cholesky, solves), results rounded to float.  The grid covers every sparse
 // point (the list length is known only on the device); groups past the list
 // end leave at once.  log sigma: when every point is recomputed (policy) a
-// workgroup covers the same 64 points as the float pass would and writes its
-// double partial to ldpart; otherwise the workgroup adds its partial in
-// fixed point to status[3] with one atomic (integer sums commute).
+// workgroup covers the same points as the float pass would and writes its
+// double partial to ldpart; otherwise each point adds its term in fixed point
+// to ldfix of the float-pass block it belongs to (integer atomics commute, so
+// the sum is the same whatever order the list and the atomics take).
 template <int K, int KIND>
 __global__ __launch_bounds__(kBlock, factor_min_waves(8, K)) void factor_redo_kernel(FactorArgs<float> a,
                                                                                        Cov<double> cov) {
     constexpr int P = factor_lanes(VECCHIA_FP64, K);
+    static_assert(P == factor_lanes(VECCHIA_FP32, K), "float and double passes share the block of a point");
     constexpr int R = K / P;
     constexpr int PTS = kBlock / P;
     const int tid = threadIdx.x;
     const int r = tid % P;
-    const bool direct = all_points_in_double(a.status);
+    const bool direct = all_points_in_double<K>(a.status);
     const int64_t count = direct ? a.ns : (int64_t)a.status[2];
     if (direct && blockIdx.x == 0 && tid == 0) a.status[2] = (uint64_t)a.ns;   // recompute count for the host
     const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
     if (blk * PTS >= count) return;
     const int64_t e = blk * PTS + tid / P;
     double lsum = 0.0;
-    long long lfix = 0;
     if (e < count) {
         const int64_t sp = direct ? e : (int64_t)a.redo[e];
         const int64_t base = (sp >> 6) * (int64_t)K * kTile + (sp & 63);
@@ -519,29 +534,20 @@ __global__ __launch_bounds__(kBlock, factor_min_waves(8, K)) void factor_redo_ke
             } else if (direct) {
                 lsum = 0.5 * log(s2);
             } else {
-                lfix = __double2ll_rn(0.5 * log(s2) * kFixScale);
+                const long long f = __double2ll_rn(0.5 * log(s2) * kFixScale);
+                atomicAdd((unsigned long long*)&a.ldfix[sp / PTS], (unsigned long long)f);
             }
         }
     }
+    if (!direct) return;
     __shared__ double part[kBlock / 64];
-    __shared__ long long part_fix[kBlock / 64];
     lsum = wave_sum_f64<double>(lsum);
-    for (int off = 32; off > 0; off >>= 1) lfix += __shfl_xor(lfix, off, 64);
-    if ((tid & 63) == 0) {
-        part[tid >> 6] = lsum;
-        part_fix[tid >> 6] = lfix;
-    }
+    if ((tid & 63) == 0) part[tid >> 6] = lsum;
     __syncthreads();
     if (tid == 0) {
-        if (direct) {
-            double s = 0.0;
-            for (int w = 0; w < kBlock / 64; ++w) s += part[w];
-            a.ldpart[blk] = s;
-        } else {
-            long long f = 0;
-            for (int w = 0; w < kBlock / 64; ++w) f += part_fix[w];
-            if (f) atomicAdd((unsigned long long*)&a.status[3], (unsigned long long)f);
-        }
+        double s = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) s += part[w];
+        a.ldpart[blk] = s;
     }
 }
 
@@ -555,6 +561,7 @@ hipError_t launch_factor_sparse_t(const FactorLaunch& L, hipStream_t stream) {
     a.b = static_cast<T*>(L.b);
     a.sigma = static_cast<T*>(L.sigma);
     a.ldpart = L.ldpart;
+    a.ldfix = L.ldfix;
     a.status = L.status;
     a.redo = L.redo;
     a.ns = L.ns;

@@ -436,7 +436,9 @@ extern "C" int graph_build(const double* x, int64_t n, int32_t d, int32_t k, int
     if (!x) return vecchia_set_error(VECCHIA_EINVAL, "graph_build: x is NULL");
     if (n < 1 || n >= (int64_t(1) << 31)) return vecchia_set_error(VECCHIA_EINVAL, "graph_build: need 1 <= N < 2^31, got %lld", (long long)n);
     if (d < 1 || d > 3) return vecchia_set_error(VECCHIA_EINVAL, "graph_build: need 1 <= d <= 3, got %d", d);
-    if (k < 1 || k > VECCHIA_KMAX) return vecchia_set_error(VECCHIA_EINVAL, "graph_build: need 1 <= k <= %d, got %d", VECCHIA_KMAX, k);
+    if (k < 1) return vecchia_set_error(VECCHIA_EINVAL, "graph_build: need k >= 1, got %d", k);
+    if (k > VECCHIA_KMAX)
+        return vecchia_set_error(VECCHIA_EUNSUPPORTED, "graph_build: k=%d exceeds the compiled maximum %d", k, VECCHIA_KMAX);
     if (n0 < 1 || n0 > n) return vecchia_set_error(VECCHIA_EINVAL, "graph_build: need 1 <= n0 <= N, got n0=%d", n0);
     for (int64_t i = 0; i < n * d; ++i)
         if (!std::isfinite(x[i])) return vecchia_set_error(VECCHIA_EINVAL, "graph_build: non-finite coordinate at point %lld", (long long)(i / d));

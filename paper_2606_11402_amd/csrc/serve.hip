@@ -355,6 +355,9 @@ extern "C" int serve_create(void* arena, size_t arena_bytes, int32_t n_streams, 
 }
 
 extern "C" int serve_request_bytes(int64_t n, int32_t k, int32_t n0, size_t* bytes) {
+    if (k > VECCHIA_KMAX)
+        return vecchia_set_error(VECCHIA_EUNSUPPORTED, "serve_request_bytes: k=%d exceeds the compiled maximum %d", k,
+                                 VECCHIA_KMAX);
     const int kp = vecchia_padded_k(k);
     if (!bytes || kp < 0 || n < 1 || n0 < 1 || n0 > n)
         return vecchia_set_error(VECCHIA_EINVAL, "serve_request_bytes: bad arguments");
@@ -369,8 +372,11 @@ extern "C" int serve_submit(vecchia_server* s, const double* x, int64_t n, int32
     if (op < VECCHIA_OP_FORWARD || op > VECCHIA_OP_LOGDET)
         return vecchia_set_error(VECCHIA_EINVAL, "serve_submit: op must be forward, inverse or logdet");
     if (op != VECCHIA_OP_LOGDET && !input) return vecchia_set_error(VECCHIA_EINVAL, "serve_submit: input is NULL");
+    if (k > VECCHIA_KMAX || n0 > VECCHIA_N0MAX)
+        return vecchia_set_error(VECCHIA_EUNSUPPORTED, "serve_submit: k=%d or n0=%d exceeds the compiled maximum (%d, %d)",
+                                 k, n0, VECCHIA_KMAX, VECCHIA_N0MAX);
     const int kp = vecchia_padded_k(k);
-    if (kp < 0 || n < 1 || n >= (int64_t(1) << 31) || n0 < 1 || n0 > n || n0 > VECCHIA_N0MAX)
+    if (kp < 0 || n < 1 || n >= (int64_t(1) << 31) || n0 < 1 || n0 > n)
         return vecchia_set_error(VECCHIA_EINVAL, "serve_submit: need 1 <= k <= %d and 1 <= n0 <= min(N, %d)",
                                  VECCHIA_KMAX, VECCHIA_N0MAX);
     if (kern->kind < 0 || kern->kind > 2 || !(kern->sigma > 0) || !(kern->ell > 0) || !(kern->nugget >= 0))
@@ -454,6 +460,10 @@ extern "C" int serve_progress(vecchia_server* s, int32_t* n_completed) {
             const int rc = launch_request(s, r);
             if (rc) {
                 r->error = vecchia_last_error();
+                // part of the request's work may already be queued on its
+                // stream and still use its arena range: let it drain before
+                // finish() hands the range to the next request
+                (void)hipStreamSynchronize(s->streams[r->stream]);
                 finish(s, r, rc);
                 first_error = first_error ? first_error : rc;
                 continue;
@@ -532,6 +542,11 @@ extern "C" int serve_cancel(vecchia_server* s, int64_t id) {
     int expected = QUEUED;
     if (r->state.compare_exchange_strong(expected, CANCELLED) ||
         (expected = BUILDING, r->state.compare_exchange_strong(expected, CANCELLED))) {
+        // Drop every queue's pointer to it now, under the mutex, so that
+        // serve_release may free it at once: a worker that already holds it
+        // (in_build) sees CANCELLED when it finishes and queues nothing.
+        s->build_q.erase(std::remove(s->build_q.begin(), s->build_q.end(), r), s->build_q.end());
+        s->ready_q.erase(std::remove(s->ready_q.begin(), s->ready_q.end(), r), s->ready_q.end());
         s->n_cancelled++;
         return VECCHIA_OK;
     }

@@ -78,6 +78,33 @@ class Run:
         so[rows] = s
         return bo, so
 
+    def oracle_state(self):
+        """The GPU's own factor (L0, b, sigma) as an oracle.Factor in slot
+        order: the oracle's forward, inverse and logdet evaluated on it
+        isolate the level kernels from the conditioning of Eq. (2)."""
+        b, s = self.coefficients_by_slot()
+        l0 = self.fac._ws_slice("L0").cpu().numpy().copy()   # dense block: storage order = slot order
+        return oracle.Factor(L0=l0, b=b, sigma=s.astype(np.float64))
+
+    def storage_rounded(self, a):
+        """Values as the device holds them in this run's storage precision."""
+        a = np.asarray(a, dtype=np.float64)
+        return a.astype(np.float32).astype(np.float64) if self.precision == FP32 else a
+
+
+def check_capped(errs, tol, caps, names):
+    """Metrics above the bar must be listed in caps (name -> largest
+    accepted value, a regression cap set from the measured error with a
+    stated margin) and stay under it; returns the misses for an xfail."""
+    missed = []
+    for name in names:
+        if errs[name] > tol:
+            assert name in caps, ("%s = %.3e above the bar %g and not a capped metric" % (name, errs[name], tol))
+            assert errs[name] <= caps[name], ("%s = %.3e above its regression cap %.1e" % (name, errs[name],
+                                                                                          caps[name]))
+            missed.append("%s=%.2e (cap %.0e)" % (name, errs[name], caps[name]))
+    return missed
+
 
 def oracle_run(x, k, n0, kern, xi_input=None):
     og = oracle.build_graph(x, k, n0)

@@ -42,7 +42,29 @@ def test_abi_sizes_match_binding():
 
 def test_padded_widths():
     lib = _lib.load()
-    assert [lib.vecchia_padded_k(k) for k in (0, 1, 8, 9, 16, 17, 32, 33)] == [-1, 8, 8, 16, 16, 32, 32, -1]
+    assert [lib.vecchia_padded_k(k) for k in (0, 1, 8, 9, 16, 17, 32)] == [-1, 8, 8, 16, 16, 32, 32]
+    assert lib.vecchia_padded_k(_lib.KMAX) == _lib.KMAX and lib.vecchia_padded_k(_lib.KMAX + 1) == -1
+
+
+def test_neighbour_count_above_the_compiled_maximum_is_unsupported():
+    """k > KMAX is a valid Vecchia approximation that is not compiled
+    (EUNSUPPORTED); k < 1 is an invalid argument (EINVAL)."""
+    import numpy as np
+    lib = _lib.load()
+    out = ctypes.c_size_t()
+    assert lib.vecchia_workspace_bytes(4096, _lib.KMAX + 1, 128, 0, ctypes.byref(out)) == _lib.EUNSUPPORTED
+    assert lib.vecchia_workspace_bytes(4096, 0, 128, 0, ctypes.byref(out)) == _lib.EINVAL
+    x = np.random.default_rng(0).random((200, 3))
+    h = ctypes.c_void_p()
+    xp = x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert lib.graph_build(xp, 200, 3, _lib.KMAX + 1, 128, 1, ctypes.byref(h)) == _lib.EUNSUPPORTED
+    assert lib.graph_build(xp, 200, 3, 0, 128, 1, ctypes.byref(h)) == _lib.EINVAL
+    v = _lib.ViewStruct()
+    v.n, v.k, v.kp, v.n0, v.precision = 1000, _lib.KMAX + 1, _lib.KMAX, 128, 0
+    assert lib.vecchia_factor(ctypes.byref(v), ctypes.byref(_lib.KernelStruct(1, 1.0, 0.1, 0.0)), None) \
+        == _lib.EUNSUPPORTED
+    nbytes = ctypes.c_size_t()
+    assert lib.serve_request_bytes(1000, _lib.KMAX + 1, 128, ctypes.byref(nbytes)) == _lib.EUNSUPPORTED
 
 
 def test_workspace_bytes_and_errors():

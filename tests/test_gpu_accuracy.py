@@ -17,45 +17,55 @@ import oracle
 import workloads
 from oracle import Kernel
 from paper_2606_11402_amd import FP32, FP64
-from gpu_helpers import Run, rel_err
+from gpu_helpers import Run, check_capped, rel_err
 
 pytestmark = pytest.mark.gpu
 
 
-def measure(x, k, kern, xi_in, precision, redo_log2=0):
+def measure(x, k, kern, xi_in, precision, redo_log2=0, og=None, fac=None):
     run = Run(x, k, 128, kern, precision, xi_in, redo_log2=redo_log2)
-    og = oracle.build_graph(x, k, 128)
-    fac = oracle.factor(og, kern)
+    og = oracle.build_graph(x, k, 128) if og is None else og
+    fac = oracle.factor(og, kern) if fac is None else fac
     xi = np.asarray(xi_in)[og.perm]
     v = oracle.forward(og, fac, xi)
-    v_in = v.astype(np.float32).astype(np.float64) if precision == FP32 else v
-    xi_gpu = run.fac.inverse(torch.from_numpy(v_in[run.g.slot]).to(run.dtype).cuda()).cpu().numpy()
+    v_in = run.storage_rounded(v)
+    xi_gpu = run.slot_order(run.fac.inverse(torch.from_numpy(v_in[run.g.slot]).to(run.dtype).cuda()).cpu().numpy())
+    v_gpu = run.slot_order(run.v.cpu().numpy())
     bad, redo = run.fac.counts()
+    state = run.oracle_state()
+    ld_state = oracle.logdet(state)
     errs = {
-        "v": rel_err(run.slot_order(run.v.cpu().numpy()), v),
-        "xi_inverse": rel_err(run.slot_order(xi_gpu), oracle.inverse(og, fac, v_in)),
+        "v": rel_err(v_gpu, v),
+        "xi_inverse": rel_err(xi_gpu, oracle.inverse(og, fac, v_in)),
         "logdet": abs(run.ld.item() - oracle.logdet(fac)) / abs(oracle.logdet(fac)),
+        "state_v": rel_err(v_gpu, oracle.forward(og, state, run.storage_rounded(xi))),
+        "state_xi_inverse": rel_err(xi_gpu, oracle.inverse(og, state, v_in)),
+        "state_logdet": abs(run.ld.item() - ld_state) / abs(ld_state),
         "not_pd": bad, "recomputed_fp64": redo, "n": len(x),
     }
-    print("accuracy", "fp32" if precision == FP32 else "fp64", errs, flush=True)
+    print("accuracy", "fp32" if precision == FP32 else "fp64", "redo_log2", redo_log2, errs, flush=True)
     return errs
 
 
 TOL = {FP32: 1e-4, FP64: 1e-10}
-LIMIT_REASON = ("float storage of K_cc values, b and v cannot represent these conditioning sets "
-                "(cond(K_cc) up to ~1e8); the errors are amplified by sum|b_m v_m| / sigma_i")
+LIMIT_REASON = ("cond(K_cc) reaches ~1e8 on these distributions; the error of the conditional mean that the "
+                "conditioning leaves in b is divided by sigma_i in the inverse; the oracle's inverse on the GPU's "
+                "own factor agrees at the bar (state_xi_inverse)")
 
 
-def judge(errs, precision, limited):
+def judge(errs, precision, caps):
     tol = TOL[precision]
     assert errs["not_pd"] == 0
-    missed = []
-    for name in ("v", "xi_inverse", "logdet"):
-        if errs[name] > tol:
-            assert name in limited, (name, errs[name])
-            missed.append("%s=%.2e" % (name, errs[name]))
+    for name in ("state_v", "state_xi_inverse", "state_logdet"):
+        assert errs[name] <= tol, (name, errs[name])
+    missed = check_capped(errs, tol, caps, ("v", "xi_inverse", "logdet"))
     if missed:
         pytest.xfail("above %g: %s; %s" % (tol, ", ".join(missed), LIMIT_REASON))
+
+
+# Regression caps (measured end-to-end error x 10, MI355X).
+CAPS_W2 = {FP32: {"xi_inverse": 1e-2}, FP64: {"xi_inverse": 1e-4}}
+CAPS_W3 = {FP32: {"xi_inverse": 1e-2}, FP64: {}}
 
 
 @pytest.mark.parametrize("precision", [FP32, FP64])
@@ -63,7 +73,7 @@ def test_workload2_radial_m32(precision):
     w = workloads.WORKLOADS[2]
     n = 1 << 15
     errs = measure(w.points(n), w.k, Kernel(w.kind, w.sigma, w.ell, w.nugget), w.xi(n), precision)
-    judge(errs, precision, ("xi_inverse",) if precision == FP64 else ("v", "xi_inverse"))
+    judge(errs, precision, CAPS_W2[precision])
 
 
 @pytest.mark.parametrize("precision", [FP32, FP64])
@@ -71,17 +81,28 @@ def test_workload3_clumped_se(precision):
     w = workloads.WORKLOADS[3]
     n = 1 << 14
     errs = measure(w.points(n), w.k, Kernel(w.kind, w.sigma, w.ell, w.nugget), w.xi(n), precision)
-    judge(errs, precision, () if precision == FP64 else ("v", "xi_inverse"))
+    judge(errs, precision, CAPS_W3[precision])
 
 
-def test_redo_threshold_sweep_reports():
-    """Sweep of the recompute threshold on workload 3's distribution: the
-    fraction recomputed in double and the errors, for the record."""
+def test_redo_threshold_sweep():
+    """Sweep of the recompute threshold 2^-bits on workload 3's distribution:
+    a smaller threshold can only send fewer points to the double recompute
+    (the same float pivots are compared with it), every setting factors
+    without failure, the level kernels agree with the oracle on their own
+    state at every setting, and the default (bits = 0 -> 8) meets the bar."""
     w = workloads.WORKLOADS[3]
     n = 1 << 13
     x, xi = w.points(n), w.xi(n)
     kern = Kernel(w.kind, w.sigma, w.ell, w.nugget)
-    for bits in (-1, 8, 12, 16, 20, 24):
-        errs = measure(x, w.k, kern, xi, FP32, redo_log2=bits)
-        print("redo_log2", bits, errs, flush=True)
+    og = oracle.build_graph(x, w.k, 128)
+    fac = oracle.factor(og, kern)
+    counts = []
+    for bits in (4, 8, 12, 16, 20, 24, -1):
+        errs = measure(x, w.k, kern, xi, FP32, redo_log2=bits, og=og, fac=fac)
         assert errs["not_pd"] == 0
+        assert errs["state_v"] <= 1e-4 and errs["state_logdet"] <= 1e-4
+        counts.append(errs["recomputed_fp64"])
+    assert all(a >= b for a, b in zip(counts, counts[1:])), counts
+    default = measure(x, w.k, kern, xi, FP32, redo_log2=0, og=og, fac=fac)
+    assert default["recomputed_fp64"] == counts[1]          # 0 selects 2^-8
+    assert default["v"] <= 1e-4 and default["logdet"] <= 1e-4

@@ -109,6 +109,9 @@ def test_adjoint_identity_large():
     assert abs(lhs - rhs) <= 1e-11 * (torch.linalg.norm(vbar) * torch.linalg.norm(v)).item()
 
 
+C4_FP32_THETA_CAP = 1e-2   # regression cap of the FP32 end-to-end theta error (measured x 10)
+
+
 def c4_loss_oracle(og, kern, xi_slot, y_slot, s2):
     f = oracle.factor(og, kern)
     v = oracle.forward(og, f, xi_slot)
@@ -178,8 +181,10 @@ def test_workload4_loss_gradients(precision):
         assert errs["theta_vs_fd"] <= 1e-5 and errs["theta_vs_oracle"] <= 1e-9
     elif errs["theta_vs_oracle"] > tol:
         # end to end, the float forward state alone moves the exact gradient
-        # by oracle_state_vs_oracle; the adjoint adds no more than tol to it
+        # by oracle_state_vs_oracle; the adjoint adds no more than tol to it.
+        # Regression cap: the measured end-to-end error times ten.
         assert errs["theta_vs_oracle"] <= errs["oracle_state_vs_oracle"] + tol
+        assert errs["theta_vs_oracle"] <= C4_FP32_THETA_CAP, errs["theta_vs_oracle"]
         pytest.xfail("FP32 theta gradient %.2e from the FP64 oracle: the float forward state (b, sigma, v) "
                      "alone accounts for %.2e; the adjoint at that state agrees to %.2e"
                      % (errs["theta_vs_oracle"], errs["oracle_state_vs_oracle"],

@@ -18,7 +18,7 @@ import oracle
 import workloads
 from oracle import Kernel, EXP, M32, SE
 from paper_2606_11402_amd import FP32, FP64, VecchiaError
-from gpu_helpers import Run, b_backward_error, oracle_run, rel_err
+from gpu_helpers import Run, b_backward_error, check_capped, oracle_run, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -28,48 +28,66 @@ TOL = {FP64: 1e-10, FP32: 1e-4}
 TOL_B_BACKWARD = {FP64: 1e-12, FP32: 1e-5}
 
 
-# Metrics that float storage or the conditioning of K_cc cannot bring under the
-# bar: they are still computed against the same tolerance, and a miss turns
-# the test into an expected failure that names the measured error and why.
-COND_LIMITED = ("the inverse subtracts the conditional mean from v and divides by sigma_i; with "
-                "cond(K_cc) ~ 1e4-1e8 the rounding of K_cc, b and v in the storage precision is "
-                "amplified by sum|b_m v_m| / sigma_i (reproduced on the CPU with an exact solve of the "
-                "rounded K_cc)")
+# End-to-end metrics that the conditioning of K_cc keeps above the bar in a
+# given test carry a regression cap (the largest accepted value: the measured
+# error times ten, so that a regression fails instead of passing as an
+# expected failure).  Every test also checks the GPU's level kernels on its own
+# factor state at the bar (state_*: the oracle's forward, inverse and logdet
+# evaluated with the GPU's L0, b and sigma), which a conditioning-limited
+# end-to-end miss leaves untouched.
+COND_LIMITED = ("b is ill-determined where cond(K_cc) is large (its forward error is cond(K_cc) times the "
+                "roundoff of its backward-stable solve), and the inverse divides the resulting error of the "
+                "conditional mean b.v[c] by sigma_i; the same b gives the oracle's inverse at the bar (state_*)")
 
 
-def check_against_oracle(x, k, n0, kern, precision, xi_in, tol=None, report=None, limited=()):
+def check_against_oracle(x, k, n0, kern, precision, xi_in, tol=None, report=None, caps=None):
     tol = TOL[precision] if tol is None else tol
+    caps = caps or {}
     run = Run(x, k, n0, kern, precision, xi_in)
     ref = oracle_run(x, k, n0, kern, xi_in)
     b, s = run.coefficients_by_slot()
     fac = ref["fac"]
+    og = ref["graph"]
+    v_gpu = run.slot_order(run.v.cpu().numpy())
     errs = {
         "b": rel_err(b, fac.b),
         "sigma": rel_err(s, fac.sigma),
-        "v": rel_err(run.slot_order(run.v.cpu().numpy()), ref["v"]),
+        "v": rel_err(v_gpu, ref["v"]),
         "xi_roundtrip": rel_err(run.slot_order(run.xi_back.cpu().numpy()), ref["xi"]),
         "logdet": abs(run.ld.item() - ref["logdet"]) / abs(ref["logdet"]),
     }
     # inverse of the oracle's own v, rounded to the storage precision; the
     # reference is the oracle's inverse of that same rounded input
-    v_in = ref["v"].astype(np.float32).astype(np.float64) if precision == FP32 else ref["v"]
+    v_in = run.storage_rounded(ref["v"])
     v_ref_storage = torch.from_numpy(v_in[run.g.slot]).to(run.dtype).cuda()
-    xi_inv = run.fac.inverse(v_ref_storage).cpu().numpy()
-    errs["xi_inverse"] = rel_err(run.slot_order(xi_inv), oracle.inverse(ref["graph"], fac, v_in))
-    errs["b_backward"] = b_backward_error(ref["graph"], kern, b)
+    xi_inv = run.slot_order(run.fac.inverse(v_ref_storage).cpu().numpy())
+    errs["xi_inverse"] = rel_err(xi_inv, oracle.inverse(og, fac, v_in))
+    errs["b_backward"] = b_backward_error(og, kern, b)
+    # state-isolated: the oracle's level operations on the GPU's own factor
+    state = run.oracle_state()
+    errs["state_v"] = rel_err(v_gpu, oracle.forward(og, state, run.storage_rounded(ref["xi"])))
+    errs["state_xi_inverse"] = rel_err(xi_inv, oracle.inverse(og, state, v_in))
+    ld_state = oracle.logdet(state)
+    errs["state_logdet"] = abs(run.ld.item() - ld_state) / abs(ld_state)
     if report is not None:
         report.update(errs)
     print("errors", precision, errs, flush=True)
     run.fac.status()
     assert errs["b_backward"] <= TOL_B_BACKWARD[precision], ("b_backward", errs["b_backward"])
-    missed = []
-    for name in ("sigma", "v", "logdet", "xi_inverse", "xi_roundtrip") + (("b",) if precision == FP64 else ()):
-        if errs[name] > tol:
-            assert name in limited, (name, errs[name])
-            missed.append("%s=%.2e" % (name, errs[name]))
+    for name in ("state_v", "state_xi_inverse", "state_logdet"):
+        assert errs[name] <= tol, (name, errs[name])
+    names = ("sigma", "v", "logdet", "xi_inverse", "xi_roundtrip") + (("b",) if precision == FP64 else ())
+    missed = check_capped(errs, tol, caps, names)
     if missed:
         pytest.xfail("above %g: %s; %s" % (tol, ", ".join(missed), COND_LIMITED))
     return run, ref, errs
+
+
+# Regression caps of the conditioning-limited end-to-end metrics (measured
+# error x 10, MI355X).
+CAPS_FP32_WIDTHS = {(SE, 16): {"xi_inverse": 1e-2}, (SE, 32): {"xi_inverse": 1e-2}}
+CAPS_C2 = {FP64: {"b": 1e-5, "xi_inverse": 1e-4}, FP32: {"xi_inverse": 1e-2, "b": 1e-2}}
+CAPS_SE_PRODUCT = {"b": 1e-5, "xi_inverse": 1e-4}
 
 
 def test_c1_plain_fp64():
@@ -113,8 +131,8 @@ def test_kernels_and_widths_fp32(kind, k):
     n = 3000 + 13 * k
     x = workloads.as_fp32_exact(workloads.uniform(n, 40 + k))
     kern = Kernel(kind, 1.0, 0.1, 1e-4 if kind == SE else 0.0)
-    limited = ("xi_inverse",) if kind == SE and k >= 16 else ()
-    check_against_oracle(x, k, 128, kern, FP32, workloads.white_noise(n, 140 + k), limited=limited)
+    caps = CAPS_FP32_WIDTHS.get((kind, k), {})
+    check_against_oracle(x, k, 128, kern, FP32, workloads.white_noise(n, 140 + k), caps=caps)
 
 
 @pytest.mark.parametrize("precision", [FP64, FP32])
@@ -125,10 +143,8 @@ def test_c2_shape_radial_m32(precision):
     x = w.points(n)
     # the radial core (radius 1e-3 against ell = 0.05) gives cond(K_cc) up to
     # ~1e9: in FP64 the forward error of b reaches ~1e-7 while its backward
-    # error, sigma, v and logdet stay at ~1e-12; in FP32 the float storage of
-    # v limits the round trip through sum |b_m v_m| / sigma_i
-    limited = ("xi_inverse", "b") if precision == FP64 else ("xi_inverse", "sigma", "v", "b", "xi_roundtrip")
-    check_against_oracle(x, w.k, 128, Kernel(M32, 1.0, 0.05), precision, w.xi(n), limited=limited)
+    # error, sigma, v and logdet stay at ~1e-12
+    check_against_oracle(x, w.k, 128, Kernel(M32, 1.0, 0.05), precision, w.xi(n), caps=CAPS_C2[precision])
 
 
 def test_se_product_form_fp64():
@@ -143,7 +159,7 @@ def test_se_product_form_fp64():
     w2 = np.sum((og.xs[og.nbr] - og.xs[128:, None, :]) ** 2, axis=-1) / kern.ell ** 2
     frac = (w2.max(axis=1) <= 1.0).mean()
     assert 0.8 < frac < 0.99                               # both assemblies occur
-    check_against_oracle(x, k, 128, kern, FP64, workloads.white_noise(n, 191), limited=("b", "xi_inverse"))
+    check_against_oracle(x, k, 128, kern, FP64, workloads.white_noise(n, 191), caps=CAPS_SE_PRODUCT)
 
 
 def test_dimension_one_and_two():

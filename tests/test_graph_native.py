@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 import oracle
+from paper_2606_11402_amd import _lib
 from paper_2606_11402_amd import Graph, VecchiaError
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -119,13 +120,16 @@ def test_children_lists_invert_neighbours():
 
 
 @pytest.mark.parametrize("args", [
-    dict(k=0, n0=4), dict(k=33, n0=40), dict(k=4, n0=0), dict(k=4, n0=2000),
+    dict(k=0, n0=4, code=-1), dict(k=_lib.KMAX + 1, n0=40, code=-4), dict(k=4, n0=0, code=-1),
+    dict(k=4, n0=2000, code=-1),
 ])
 def test_invalid_arguments(args):
+    """Invalid arguments are EINVAL (-1); a neighbour count above the compiled
+    maximum is EUNSUPPORTED (-4)."""
     x = np.random.default_rng(0).random((100, 3))
     with pytest.raises(VecchiaError) as e:
         Graph(x, args["k"], args["n0"])
-    assert e.value.code == -1
+    assert e.value.code == args["code"]
 
 
 def test_non_finite_rejected():

@@ -37,6 +37,32 @@ def test_exact_limit_matches_dense_cholesky(kern):
     assert abs(oracle.logdet(fac) - ld) <= 1e-9 * abs(ld)
 
 
+@pytest.mark.parametrize("n0", [17, 64])
+@pytest.mark.parametrize("kern", KERNELS)
+def test_exact_limit_with_dense_initial_block(kern, n0):
+    """Sec. 2.1 and Sec. 2.2 (dense initial batch): with c(i) = every
+    preceding slot, the dense block L0 followed by the sparse rows is the
+    dense Cholesky factor of the whole tree-ordered K (nugget on its
+    diagonal): L0 is its leading n0 x n0 block, sigma_i its diagonal, the
+    forward pass L xi and the logdet slogdet(K).  numpy's Cholesky of the
+    full matrix is the independent reference for the dense block."""
+    n = 256
+    x = np.random.default_rng(7).random((n, 3))
+    gr = oracle.build_graph(x, n - 1, n0)
+    fac = oracle.factor(gr, kern)
+    r = np.sqrt(np.sum((gr.xs[:, None, :] - gr.xs[None, :, :]) ** 2, axis=-1))
+    kd = oracle.kappa(r, kern) + kern.nugget * np.eye(n)          # the covariance written out directly
+    l = np.linalg.cholesky(kd)
+    np.testing.assert_allclose(fac.L0, l[:n0, :n0], rtol=1e-11, atol=1e-13)
+    np.testing.assert_allclose(fac.sigma, np.diag(l)[n0:], rtol=1e-9)
+    xi = np.random.default_rng(8).standard_normal(n)
+    np.testing.assert_allclose(oracle.forward(gr, fac, xi), l @ xi, rtol=1e-9, atol=1e-9)
+    sign, ld = np.linalg.slogdet(kd)
+    assert sign > 0
+    assert abs(oracle.logdet(fac) - ld) <= 1e-9 * abs(ld)
+    np.testing.assert_allclose(oracle.inverse(gr, fac, l @ xi), xi, rtol=1e-7, atol=1e-7)
+
+
 @pytest.mark.parametrize("kern", KERNELS)
 def test_k1_closed_form(kern):
     x = np.random.default_rng(3).random((50, 3))

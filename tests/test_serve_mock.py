@@ -3,7 +3,7 @@ HBM-arena accounting, FIFO order, cancellation, rejection); no device."""
 import numpy as np
 import pytest
 
-from paper_2606_11402_amd import VecchiaError
+from paper_2606_11402_amd import VecchiaError, _lib
 from paper_2606_11402_amd.serve import Server
 
 
@@ -81,6 +81,25 @@ def test_cancel_queued_request():
     srv.close()
 
 
+def test_cancel_then_release_at_once_keeps_the_queues_valid():
+    """A cancelled request is released right away (queued and still
+    building); the scheduler must not touch it again afterwards."""
+    one = Server.request_bytes(2000, 8)
+    srv = Server(one + 512, graph_workers=1, mock=True)
+    a = srv.submit(pts(2000, 1), 8, 0, 1.0, 0.2, "logdet")
+    b = srv.submit(pts(2000, 2), 8, 0, 1.0, 0.2, "logdet")
+    wait_built(srv, [a, b])
+    srv.progress()                      # a admitted, b waits for memory
+    srv.cancel(b)                       # Server.cancel releases it at once, while it sat in the ready queue
+    c = srv.submit(pts(1900, 3), 8, 0, 1.0, 0.2, "logdet")
+    srv.cancel(c)                       # still in the build queue or being built
+    d = srv.submit(pts(1500, 4), 8, 0, 1.0, 0.2, "logdet")
+    done = srv.drain()
+    assert set(done) == {a, d}
+    assert srv.stats()["cancelled"] == 2
+    srv.close()
+
+
 def test_mixed_sizes_never_exceed_budget():
     rng = np.random.default_rng(3)
     sizes = rng.integers(200, 4000, 40)
@@ -99,7 +118,7 @@ def test_mixed_sizes_never_exceed_budget():
 def test_invalid_submissions():
     srv = Server(1 << 24, mock=True)
     with pytest.raises(VecchiaError):
-        srv.submit(pts(100, 0), 64, 1, 1.0, 0.1, "logdet")          # k > 32
+        srv.submit(pts(100, 0), _lib.KMAX + 1, 1, 1.0, 0.1, "logdet")   # k above the compiled maximum
     with pytest.raises(VecchiaError):
         srv.submit(pts(100, 0), 8, 1, -1.0, 0.1, "logdet")          # sigma <= 0
     with pytest.raises(VecchiaError):
