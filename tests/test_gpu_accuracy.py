@@ -63,9 +63,11 @@ def judge(errs, precision, caps):
         pytest.xfail("above %g: %s; %s" % (tol, ", ".join(missed), LIMIT_REASON))
 
 
-# Regression caps (measured end-to-end error x 10, MI355X).
-CAPS_W2 = {FP32: {"xi_inverse": 1e-2}, FP64: {"xi_inverse": 1e-4}}
-CAPS_W3 = {FP32: {"xi_inverse": 1e-2}, FP64: {}}
+# Regression caps: ten times the end-to-end error measured on MI355X (FP64
+# inverse on the radial cloud 3.55e-8; FP32 inverse on the clumped cloud
+# 2.72e-4, float storage of v divided by sigma_i at the nugget level).
+CAPS_W2 = {FP32: {}, FP64: {"xi_inverse": 3.6e-7}}
+CAPS_W3 = {FP32: {"xi_inverse": 2.7e-3}, FP64: {}}
 
 
 @pytest.mark.parametrize("precision", [FP32, FP64])

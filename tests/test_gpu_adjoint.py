@@ -109,7 +109,7 @@ def test_adjoint_identity_large():
     assert abs(lhs - rhs) <= 1e-11 * (torch.linalg.norm(vbar) * torch.linalg.norm(v)).item()
 
 
-C4_FP32_THETA_CAP = 1e-2   # regression cap of the FP32 end-to-end theta error (measured x 10)
+C4_FP32_THETA_CAP = 1e-3   # regression cap of the FP32 end-to-end theta error; it meets 1e-4 today (the policy factors this cloud in double)
 
 
 def c4_loss_oracle(og, kern, xi_slot, y_slot, s2):
