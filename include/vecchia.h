@@ -205,6 +205,24 @@ int vecchia_backward(const vecchia_view* view, const vecchia_kernel* kern,
                      double logdet_bar, void* xi_bar, void* v_bar_out, double* theta_bar,
                      void* scratch, size_t scratch_bytes, void* stream);
 
+/* vecchia_backward for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same derivatives, computed by the same kernels, with the scratch taken
+ * from a fixed device array inside the library instead of a caller buffer.
+ * Every GPU the library runs on holds its own copy of that array (64 MiB,
+ * vecchia_backward_noalloc_max_bytes) from the library's load until the
+ * process ends; a view whose vecchia_backward_scratch_bytes exceeds it (about
+ * 8 million points) is rejected with VECCHIA_ENOMEM before anything is
+ * launched.  The call allocates nothing (with per-kernel timing off).  All
+ * calls on one GPU share the array and it keeps the last call's contents:
+ * calls that overlap on one GPU (other streams, other threads) race; nothing
+ * in it needs to start at zero.  Other arguments and errors as
+ * vecchia_backward. */
+int vecchia_backward_noalloc_max_bytes(size_t* bytes);
+int vecchia_backward_noalloc(const vecchia_view* view, const vecchia_kernel* kern,
+                             const void* xi, const void* v, const void* v_bar, const void* xi_bar_in,
+                             double logdet_bar, void* xi_bar, void* v_bar_out, double* theta_bar, void* stream);
+
 /* Synchronises `stream`, then reports how many points of the last
  * vecchia_factor had a non-positive pivot or variance (not_pd) and, for
  * VECCHIA_FP32, how many were recomputed in double (recomputed). */
