@@ -298,7 +298,7 @@ def main():
     inv_gbs = bpp * ns / (inv_sparse_ms * 1e-3) / 1e9
     levels_ms = sum(t for name, (t, _) in prof.items()
                     if name.startswith("forward_") and name != "forward_dense") / steps
-    kp = 8 if k <= 8 else (16 if k <= 16 else 32)
+    kp = 8 if k <= 8 else (16 if k <= 16 else (32 if k <= 32 else 64))
     digest = source_digest(kernel_sources("f32" if precision == FP32 else "f64", kp))
     tr = read_traffic(dom, w.name if args.n is None and args.k is None else None, digest)
     traffic, traffic_detail = None, None

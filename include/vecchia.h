@@ -25,7 +25,7 @@
  *   - Tiled layout of the per-point k-vectors (neighbours, coefficients): for
  *     64 consecutive sparse points, entry m of each point is contiguous:
  *     element (s', m) lives at ((s' / 64) * kp + m) * 64 + s' % 64, where kp
- *     is k rounded up to a compiled width (8, 16 or 32); unused entries hold
+ *     is k rounded up to a compiled width (8, 16, 32 or 64); unused entries hold
  *     the neighbour index -1 and the coefficient 0.  Array length:
  *     ceil(Ns / 64) * kp * 64.
  *   - Precision: VECCHIA_FP64 computes everything in double.  VECCHIA_FP32
@@ -50,14 +50,14 @@ extern "C" {
 #define VECCHIA_EINVAL       -1   /* bad argument, detected on the host before any launch */
 #define VECCHIA_ENOMEM       -2   /* host allocation failed or workspace too small */
 #define VECCHIA_ENOTPD       -3   /* a covariance block was not positive definite */
-#define VECCHIA_EUNSUPPORTED -4   /* valid but not compiled (e.g. k > 32, n0 > 128) */
+#define VECCHIA_EUNSUPPORTED -4   /* valid but not compiled (e.g. k > 64, n0 > 128) */
 #define VECCHIA_EHIP         -5   /* a HIP runtime call failed */
 #define VECCHIA_EBUDGET      -6   /* serving admission: request exceeds the HBM budget */
 
 #define VECCHIA_FP64 0
 #define VECCHIA_FP32 1
 
-#define VECCHIA_KMAX  32          /* largest compiled neighbour count */
+#define VECCHIA_KMAX  64          /* largest compiled neighbour count */
 #define VECCHIA_N0MAX 128         /* largest dense block (FP64 n0 x n0 in one workgroup's LDS) */
 
 /* ---- covariance ---------------------------------------------------------- */
@@ -305,7 +305,7 @@ int serve_stats(vecchia_server* s, vecchia_serve_stats* out);
  * except the caller's arena. */
 void serve_destroy(vecchia_server* s);
 
-/* Padded width used for a neighbour count k (8, 16 or 32), or -1. */
+/* Padded width used for a neighbour count k (8, 16, 32 or 64), or -1. */
 int32_t vecchia_padded_k(int32_t k);
 
 /* Per-kernel timing: when enabled, every launch made by the library is

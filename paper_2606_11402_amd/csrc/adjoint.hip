@@ -19,62 +19,14 @@
 // h = L0^T gamma, M = Phi(h xi0^T) + ldbar I (lower triangle, diagonal
 // halved), theta_bar += sum_pq (L0^-T M L0^-1)_pq dK0_pq.
 // All theta sums are accumulated in double and reduced in a fixed order.
-#include <algorithm>
-
-#include "factor_kernel.h"
+#include "adjoint.h"
 
 namespace vk {
-
-// kappa(r) and d kappa / d ell (no nugget), double.
-template <int KIND>
-__device__ __forceinline__ void cov_and_dell(double r2, const Cov<double>& c, double& kap, double& dell) {
-    if constexpr (KIND == 0) {
-        const double r = sqrt(r2);
-        kap = c.s2 * exp(-r * c.inv_ell);
-        dell = kap * r * c.inv_ell * c.inv_ell;
-    } else if constexpr (KIND == 1) {
-        const double a = sqrt(r2) * c.c_m32;
-        const double e = exp(-a);
-        kap = c.s2 * (1.0 + a) * e;
-        dell = c.s2 * a * a * e * c.inv_ell;
-    } else {
-        kap = c.s2 * exp(r2 * c.c_se);
-        dell = kap * r2 * c.inv_ell * c.inv_ell * c.inv_ell;
-    }
-}
-
-template <typename TS>
-struct AdjArgs {
-    const TS* x;
-    const int32_t* nbr;
-    const int64_t* child_ptr;
-    const int32_t* child;
-    const TS* b;
-    const TS* sigma;
-    const double* l0;
-    const TS* xi;           // the pair (xi, v)
-    const TS* v;
-    const TS* vbar;         // may be null
-    const TS* xibar_in;     // may be null
-    double* w;              // scratch, N: the reverse sweep, double in both precisions
-    TS* xibar;              // output (forward part)
-    TS* vbar_out;           // output (inverse part)
-    double* t0;             // scratch, n0: L0^-T xibar0
-    double* theta_part;     // scratch, 2 per block of the theta kernel
-    double* theta_dense;    // scratch, 2
-    double* theta_out;      // output, 2
-    int64_t n, ns, nblocks;
-    int n0, kp;
-    double ldbar;
-    double sigma_amp;
-    double diag;            // K_ii = sigma^2 + nugget
-    Cov<double> cov;
-};
 
 // ---- reverse sweep of one batch: w_j = vbar_j + sum_children b w_child
 template <typename TS, int KP>
 __global__ __launch_bounds__(kBlock) void adj_sweep_kernel(AdjArgs<TS> a, int64_t j_begin, int64_t j_end) {
-    constexpr int SH = KP == 8 ? 3 : (KP == 16 ? 4 : 5);
+    constexpr int SH = KP == 8 ? 3 : (KP == 16 ? 4 : (KP == 32 ? 5 : 6));
     const int64_t j = j_begin + (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (j >= j_end) return;
     double acc = (double)a.vbar[j];
@@ -91,7 +43,7 @@ __global__ __launch_bounds__(kBlock) void adj_sweep_kernel(AdjArgs<TS> a, int64_
 // ---- inverse part: vbar_j = z_j - sum_children b z_child, z = xibar / sigma
 template <typename TS, int KP>
 __global__ __launch_bounds__(kBlock) void adj_inverse_kernel(AdjArgs<TS> a) {
-    constexpr int SH = KP == 8 ? 3 : (KP == 16 ? 4 : 5);
+    constexpr int SH = KP == 8 ? 3 : (KP == 16 ? 4 : (KP == 32 ? 5 : 6));
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (j >= a.n) return;
     double acc = j >= a.n0 ? (double)a.xibar_in[j] / (double)a.sigma[j - a.n0] : 0.0;
@@ -120,28 +72,6 @@ __global__ __launch_bounds__(VECCHIA_N0MAX) void adj_dense_inverse_kernel(AdjArg
     if (i < n0) {
         a.t0[i] = t[i];
         a.vbar_out[i] = (TS)((double)a.vbar_out[i] + t[i]);
-    }
-}
-
-__device__ __forceinline__ void block_sum2(double& s0, double& s1, double* sh) {
-    for (int off = 32; off > 0; off >>= 1) {
-        s0 += __shfl_xor(s0, off, 64);
-        s1 += __shfl_xor(s1, off, 64);
-    }
-    const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        sh[2 * wv] = s0;
-        sh[2 * wv + 1] = s1;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double a0 = 0.0, a1 = 0.0;
-        for (int w = 0; w < nw; ++w) {
-            a0 += sh[2 * w];
-            a1 += sh[2 * w + 1];
-        }
-        s0 = a0;
-        s1 = a1;
     }
 }
 
@@ -385,8 +315,12 @@ static hipError_t backward_t(const BackwardLaunch& p, hipStream_t s) {
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (a.nblocks > 0) {
-        hipLaunchKernelGGL((adj_theta_kernel<TS, KP, KIND>), dim3((unsigned)a.nblocks), dim3(kBlock), 0, s, a);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if constexpr (KP == 64) {
+            if ((e = launch_adj_theta_wide<TS>(a, KIND, s)) != hipSuccess) return e;
+        } else {
+            hipLaunchKernelGGL((adj_theta_kernel<TS, KP, KIND>), dim3((unsigned)a.nblocks), dim3(kBlock), 0, s, a);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
     }
     hipLaunchKernelGGL((adj_dense_kernel<TS, KIND>), dim3(1), dim3(VECCHIA_N0MAX), 0, s, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -411,6 +345,7 @@ static hipError_t backward_width(const BackwardLaunch& p, hipStream_t s) {
         case 8: return backward_kind<TS, 8>(p, s);
         case 16: return backward_kind<TS, 16>(p, s);
         case 32: return backward_kind<TS, 32>(p, s);
+        case 64: return backward_kind<TS, 64>(p, s);
         default: return hipErrorInvalidValue;
     }
 }

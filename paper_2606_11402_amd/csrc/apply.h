@@ -12,9 +12,10 @@ hipError_t launch_forward_dense(int precision, const double* l0, int n0, const v
 hipError_t launch_forward_level(int precision, int kp, const int32_t* nbr, const void* b, const void* sigma,
                                 const void* xi, void* v, int n0, int64_t s_begin, int64_t s_end, hipStream_t stream);
 constexpr int kRunThreads = 1024;        // workgroup of the small-batch runs
-// FP64 rows at k = 32 need more than the 128 registers per lane of 16 waves per CU
+// FP64 rows at k = 32 need more than the 128 registers per lane of 16 waves
+// per CU; rows of 64 entries more than the 256 of 8 waves
 __host__ __device__ constexpr int run_threads(int elem_bytes, int kp) {
-    return elem_bytes == 8 && kp == 32 ? kRunThreads / 2 : kRunThreads;
+    return kp == 64 ? kRunThreads / 4 : (elem_bytes == 8 && kp == 32 ? kRunThreads / 2 : kRunThreads);
 }
 constexpr int64_t kRunMaxPoints = 512;   // a batch this small joins a run
 constexpr int64_t kRunLdsBytes = 65536;  // LDS copy of the positions [lo, run_end) a run reads and writes

@@ -148,6 +148,10 @@ static hipError_t launch_run_t(int kp, const int32_t* nbr, const void* b, const 
             hipLaunchKernelGGL((forward_run_kernel<T, 32>), dim3(1), dim3(run_threads(sizeof(T), 32)), lds, s, nbr,
                                bp, sp, ip, op, n0, level_ptr_dev, l_begin, l_end, lo);
             break;
+        case 64:
+            hipLaunchKernelGGL((forward_run_kernel<T, 64>), dim3(1), dim3(run_threads(sizeof(T), 64)), lds, s, nbr,
+                               bp, sp, ip, op, n0, level_ptr_dev, l_begin, l_end, lo);
+            break;
         default:
             return hipErrorInvalidValue;
     }
@@ -183,6 +187,10 @@ static hipError_t launch_apply_t(int kp, const int32_t* nbr, const void* b, cons
             break;
         case 32:
             hipLaunchKernelGGL((apply_kernel<T, 32, INVERSE>), dim3((unsigned)nblocks), dim3(kBlock), 0, s, nbr, bp,
+                               sp, ip, op, n0, t0, s_begin, s_end, nblocks);
+            break;
+        case 64:
+            hipLaunchKernelGGL((apply_kernel<T, 64, INVERSE>), dim3((unsigned)nblocks), dim3(kBlock), 0, s, nbr, bp,
                                sp, ip, op, n0, t0, s_begin, s_end, nblocks);
             break;
         default:
@@ -288,6 +296,8 @@ hipError_t launch_factor_sparse_f32_k32(const FactorLaunch& a, hipStream_t s);
 hipError_t launch_factor_sparse_f64_k8(const FactorLaunch& a, hipStream_t s);
 hipError_t launch_factor_sparse_f64_k16(const FactorLaunch& a, hipStream_t s);
 hipError_t launch_factor_sparse_f64_k32(const FactorLaunch& a, hipStream_t s);
+hipError_t launch_factor_sparse_f32_k64(const FactorLaunch& a, hipStream_t s);
+hipError_t launch_factor_sparse_f64_k64(const FactorLaunch& a, hipStream_t s);
 
 hipError_t launch_factor_sparse(const FactorLaunch& a, hipStream_t s) {
     const bool f32 = a.precision == VECCHIA_FP32;
@@ -295,6 +305,7 @@ hipError_t launch_factor_sparse(const FactorLaunch& a, hipStream_t s) {
         case 8: return f32 ? launch_factor_sparse_f32_k8(a, s) : launch_factor_sparse_f64_k8(a, s);
         case 16: return f32 ? launch_factor_sparse_f32_k16(a, s) : launch_factor_sparse_f64_k16(a, s);
         case 32: return f32 ? launch_factor_sparse_f32_k32(a, s) : launch_factor_sparse_f64_k32(a, s);
+        case 64: return f32 ? launch_factor_sparse_f32_k64(a, s) : launch_factor_sparse_f64_k64(a, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -21,9 +21,13 @@ constexpr uint64_t kStatusNone = ~0ull;
 // (P*R*(R+1)/2 values per lane, R = kp/P) stays in registers.  Groups of 4
 // exchange values with DPP quad permutes (VALU); FP64 at kp = 32 also uses 4
 // lanes, which needs the accumulation registers of one wave per SIMD (groups
-// of 8 would need ds_swizzle round trips through the LDS unit instead).
+// of 8 would need ds_swizzle round trips through the LDS unit instead).  At
+// kp = 64 four lanes would hold 528 values each, so a point takes a whole
+// wave (lane i owns row i, factor_wide.h).  Both precisions use the same P at
+// every width, so the float and the double passes put a point in the same
+// block.
 __host__ __device__ constexpr int factor_lanes(int precision, int kp) {
-    return kp <= 8 ? 1 : 4;
+    return kp <= 8 ? 1 : (kp <= 32 ? 4 : 64);
 }
 
 // Waves per SIMD that the register allocation of a factor kernel must allow.

@@ -3,10 +3,11 @@
 // written (row and bank masks 0xF, bound control on), so no old value is
 // needed.
 //
-// A group of P lanes (P = 1, 2, 4 or 8) works on one point; lane r of the
-// group owns matrix rows i = p*P + r.  Values owned by another lane of the
+// A group of P lanes (P = 1, 2, 4, 8, 16 or 32) works on one point; lane r of
+// the group owns matrix rows i = p*P + r.  Values owned by another lane of the
 // group are read with DPP quad permutes (P <= 4: a modifier of a VALU move,
-// no memory pipe) or with ds_swizzle in bit mode (P = 8, inside groups of 32).
+// no memory pipe) or with ds_swizzle in bit mode (P >= 8: the LDS crossbar,
+// inside each half of the wave; no LDS memory is used).
 // All selectors are compile-time constants, so the loops that use them are
 // unrolled with static_for.
 #pragma once
@@ -28,7 +29,7 @@ __device__ __forceinline__ void static_for(F&& f) {
 // 32-bit value of lane S of this lane's group.
 template <int P, int S>
 __device__ __forceinline__ int group_bcast_i32(int v) {
-    static_assert(P == 1 || P == 2 || P == 4 || P == 8, "group size");
+    static_assert(P == 1 || P == 2 || P == 4 || P == 8 || P == 16 || P == 32, "group size");
     static_assert(S >= 0 && S < P, "source lane");
     if constexpr (P == 1) {
         return v;
@@ -40,13 +41,16 @@ __device__ __forceinline__ int group_bcast_i32(int v) {
         constexpr int ctrl = S | (S << 2) | (S << 4) | (S << 6);
         return __builtin_amdgcn_mov_dpp(v, ctrl, 0xF, 0xF, true);
     } else {
-        // bit mode: lane' = (lane & and_mask) | or_mask, within 32 lanes
-        constexpr int pattern = 0x18 | (S << 5);
+        // bit mode: lane' = (lane & and_mask) | or_mask, within 32 lanes; the
+        // and_mask keeps the bits above the group (group of 8: bits 3-4,
+        // group of 16: bit 4, group of 32: none)
+        constexpr int and_mask = P == 8 ? 0x18 : (P == 16 ? 0x10 : 0x00);
+        constexpr int pattern = and_mask | (S << 5);
         return __builtin_amdgcn_ds_swizzle(v, pattern);
     }
 }
 
-// 32-bit value of the lane whose index differs by X (X in {1, 2, 4}).
+// 32-bit value of the lane whose index differs by X (X in {1, 2, 4, 8, 16}).
 template <int X>
 __device__ __forceinline__ int group_xor_i32(int v) {
     if constexpr (X == 1) {
@@ -54,8 +58,8 @@ __device__ __forceinline__ int group_xor_i32(int v) {
     } else if constexpr (X == 2) {
         return __builtin_amdgcn_mov_dpp(v, 2 | (3 << 2) | (0 << 4) | (1 << 6), 0xF, 0xF, true);
     } else {
-        static_assert(X == 4, "xor distance");
-        return __builtin_amdgcn_ds_swizzle(v, 0x1F | (4 << 10));
+        static_assert(X == 4 || X == 8 || X == 16, "xor distance");
+        return __builtin_amdgcn_ds_swizzle(v, 0x1F | (X << 10));
     }
 }
 
@@ -97,6 +101,8 @@ __device__ __forceinline__ T group_sum(T v) {
     if constexpr (P >= 2) v = v + group_xor<1>(v);
     if constexpr (P >= 4) v = v + group_xor<2>(v);
     if constexpr (P >= 8) v = v + group_xor<4>(v);
+    if constexpr (P >= 16) v = v + group_xor<8>(v);
+    if constexpr (P >= 32) v = v + group_xor<16>(v);
     return v;
 }
 

@@ -28,7 +28,8 @@ extern "C" int32_t vecchia_padded_k(int32_t k) {
     if (k < 1 || k > VECCHIA_KMAX) return -1;
     if (k <= 8) return 8;
     if (k <= 16) return 16;
-    return 32;
+    if (k <= 32) return 32;
+    return 64;
 }
 
 extern "C" int vecchia_abi_sizes(size_t* view_bytes, size_t* kernel_bytes) {

@@ -49,7 +49,7 @@ def theta_err(a, ref):
 
 
 @pytest.mark.parametrize("kind", [EXP, M32, SE])
-@pytest.mark.parametrize("k", [8, 16, 32])
+@pytest.mark.parametrize("k", [8, 16, 32, 64])
 def test_forward_vjp_fp64(kind, k):
     c = Case(900 + 3 * k, k, 48, Kernel(kind, 1.2, 0.2, 1e-5 if kind == SE else 0.0), FP64, 200 + k)
     xi = c.rng.standard_normal(c.g.n)

@@ -91,6 +91,9 @@ def check_against_oracle(x, k, n0, kern, precision, xi_in, tol=None, report=None
 # core (inverse 2.98e-4, round trip 1.02e-3).  The squared-exponential
 # product form: b 1.56e-10, inverse 8.75e-10.
 CAPS_FP32_WIDTHS = {}
+# squared exponential with 64 neighbours (nugget 1e-6): the inverse 2.18e-10,
+# b's backward error 1.9e-16, the state-isolated inverse 1.5e-13
+CAPS_FP64_WIDTHS = {(SE, 64): {"xi_inverse": 2.2e-9}}
 CAPS_C2 = {FP64: {"b": 1.3e-6, "xi_inverse": 3.1e-7}, FP32: {"xi_inverse": 3.0e-3, "xi_roundtrip": 1.0e-2}}
 CAPS_SE_PRODUCT = {"b": 1.6e-9, "xi_inverse": 8.8e-9}
 
@@ -101,10 +104,11 @@ def test_c1_plain_fp64():
     check_against_oracle(w.points(), w.k, 128, Kernel(EXP, 1.0, 0.1), FP64, w.xi())
 
 
-def test_exact_limit_dense_cholesky_fp64():
+@pytest.mark.parametrize("n", [33, 65])
+def test_exact_limit_dense_cholesky_fp64(n):
     """Conditioning on every preceding point (k = N-1, n0 = 1, padded rows)
-    reproduces the dense Cholesky factor (Sec. 2.1)."""
-    n = 33
+    reproduces the dense Cholesky factor (Sec. 2.1); N = 65 conditions the
+    last point on 64 neighbours, the widest compiled set."""
     x = workloads.uniform(n, 21)
     kern = Kernel(M32, 1.0, 0.3)
     xi = workloads.white_noise(n, 121)
@@ -122,16 +126,16 @@ def test_exact_limit_dense_cholesky_fp64():
 
 
 @pytest.mark.parametrize("kind", [EXP, M32, SE])
-@pytest.mark.parametrize("k", [5, 8, 12, 16, 20, 32])
+@pytest.mark.parametrize("k", [5, 8, 12, 16, 20, 32, 48, 64])
 def test_kernels_and_widths_fp64(kind, k):
     n = 1500 + 7 * k                          # ragged last tile
     x = workloads.uniform(n, 30 + k)
     kern = Kernel(kind, 1.3, 0.15, 1e-6 if kind == SE else 0.0)
-    check_against_oracle(x, k, 64, kern, FP64, workloads.white_noise(n, 130 + k))
+    check_against_oracle(x, k, 64, kern, FP64, workloads.white_noise(n, 130 + k), caps=CAPS_FP64_WIDTHS.get((kind, k)))
 
 
 @pytest.mark.parametrize("kind", [EXP, M32, SE])
-@pytest.mark.parametrize("k", [8, 16, 32])
+@pytest.mark.parametrize("k", [8, 16, 32, 64])
 def test_kernels_and_widths_fp32(kind, k):
     n = 3000 + 13 * k
     x = workloads.as_fp32_exact(workloads.uniform(n, 40 + k))

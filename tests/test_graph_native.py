@@ -47,6 +47,8 @@ def test_golden_1d():
     (777, 3, 32, 1, 4),        # padded rows: n0 < k
     (64, 3, 8, 64, 5),         # dense block only
     (65, 3, 8, 64, 6),         # one sparse point
+    (1500, 3, 64, 64, 12),     # the widest compiled neighbour count
+    (300, 3, 64, 1, 13),       # k = 64 with padded rows
 ])
 def test_bit_exact_against_oracle(n, d, k, n0, seed):
     x = np.random.default_rng(seed).random((n, d))
