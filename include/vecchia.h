@@ -182,6 +182,30 @@ int vecchia_factor(vecchia_view* view, const vecchia_kernel* kern, void* stream)
  * workgroup barrier between batches. */
 int vecchia_forward(const vecchia_view* view, const void* xi, void* v, void* stream);
 
+/* Alg. 1 as written, fused and on the fly (Sec. 2.3, Implementation: the
+ * per-point quantities are computed where they are used instead of being
+ * stored): v[0:n0] = L0 xi[0:n0] with L0 = chol(K[0:n0, 0:n0]), then for every
+ * batch l = 1..L in order, each point i assembles K_cc, k_ci and K_ii from the
+ * coordinates (view->x, view->nbr), factors K_cc = L L^T, solves y = L^-1 k_ci
+ * and w = L^-1 v[c(i)] and sets
+ *     v_i = y . w + sigma_i xi_i,   sigma_i^2 = K_ii - y . y,
+ * which is Eq. (2)'s b_i . v[c(i)] + sigma_i xi_i without forming b_i.  No
+ * coefficient or sigma is stored: the workspace (vecchia_fused_workspace_bytes,
+ * 256-byte aligned, view->workspace / workspace_bytes) holds L0, per-tile log
+ * sigma sums and a status word, O(n0^2 + N/8) bytes instead of the factor's
+ * O(N k).  The arithmetic is double for both storage precisions; xi, v and
+ * the coordinates are stored per view->precision, in storage order.  If
+ * logdet (device, 1 double) is not NULL it receives the log-determinant of the
+ * same pass (as vecchia_logdet).  The rest of the view is as for
+ * vecchia_forward; view->kernel is not read.  A non-positive pivot or variance
+ * is recorded for vecchia_fused_status.  Errors: EINVAL, ENOMEM (workspace
+ * too small), EUNSUPPORTED, EHIP. */
+int vecchia_fused_workspace_bytes(int64_t n, int32_t k, int32_t n0, int32_t precision, size_t* bytes);
+int vecchia_forward_fused(const vecchia_view* view, const vecchia_kernel* kern, const void* xi, void* v,
+                          double* logdet, void* stream);
+/* As vecchia_status, for a view whose workspace holds a fused forward. */
+int vecchia_fused_status(const vecchia_view* view, void* stream, int64_t* first_bad_slot);
+
 /* Inverse application xi = F^-1(v): xi[0:n0] = L0^-1 v[0:n0] and
  * xi_i = (v_i - b_i . v[c(i)]) / sigma_i for every sparse point at once. */
 int vecchia_inverse(const vecchia_view* view, const void* v, void* xi, void* stream);

@@ -13,6 +13,7 @@
 #include "apply.h"
 #include "lanes.h"
 
+#include <algorithm>
 #include <type_traits>
 
 namespace vk {
@@ -279,6 +280,17 @@ __global__ __launch_bounds__(kLdThreads) void logdet_final_kernel(const double* 
         a.add(*ld0);
         out[0] = 2.0 * (a.s + a.c);
     }
+}
+
+__global__ void zero_u64_kernel(uint64_t* __restrict__ p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0;
+}
+
+hipError_t launch_zero_u64(void* p, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(zero_u64_kernel, dim3((unsigned)blocks), dim3(256), 0, s, static_cast<uint64_t*>(p), n);
+    return hipGetLastError();
 }
 
 hipError_t launch_logdet(const double* ldpart, const long long* ldfix, int64_t nparts, const double* ld0,

@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "apply.h"
+#include "fused_kernel.h"
 #include "status.h"
 
 using namespace vk;
@@ -83,7 +84,9 @@ int check_kernel(const vecchia_kernel* k) {
     return VECCHIA_OK;
 }
 
-int check_view(const vecchia_view* v, Layout* lay, const char* who) {
+// Checks shared by the stored-factor view and the fused forward's view
+// (everything but the workspace size).
+int check_view_common(const vecchia_view* v, const char* who) {
     if (!v) return vecchia_set_error(VECCHIA_EINVAL, "%s: view is NULL", who);
     if (v->n < 1 || v->n >= (int64_t(1) << 31)) return vecchia_set_error(VECCHIA_EINVAL, "%s: need 1 <= N < 2^31", who);
     if (v->k < 1) return vecchia_set_error(VECCHIA_EINVAL, "%s: need k >= 1", who);
@@ -105,11 +108,26 @@ int check_view(const vecchia_view* v, Layout* lay, const char* who) {
         return vecchia_set_error(VECCHIA_EINVAL, "%s: level_ptr must start 0, n0 and end at N", who);
     for (int l = 1; l <= v->n_levels; ++l)
         if (lp[l + 1] < lp[l]) return vecchia_set_error(VECCHIA_EINVAL, "%s: level_ptr not ascending at %d", who, l);
+    if (reinterpret_cast<uintptr_t>(v->workspace) & 255)
+        return vecchia_set_error(VECCHIA_EINVAL, "%s: workspace must be 256-byte aligned", who);
+    return VECCHIA_OK;
+}
+
+int check_view(const vecchia_view* v, Layout* lay, const char* who) {
+    const int rc = check_view_common(v, who);
+    if (rc) return rc;
     *lay = workspace_layout(v->n, v->kp, v->n0, v->precision);
     if (v->workspace_bytes < lay->total)
         return vecchia_set_error(VECCHIA_ENOMEM, "%s: workspace has %zu bytes, needs %zu", who, v->workspace_bytes, lay->total);
-    if (reinterpret_cast<uintptr_t>(v->workspace) & 255)
-        return vecchia_set_error(VECCHIA_EINVAL, "%s: workspace must be 256-byte aligned", who);
+    return VECCHIA_OK;
+}
+
+int check_fused_view(const vecchia_view* v, FusedLayout* lay, const char* who) {
+    const int rc = check_view_common(v, who);
+    if (rc) return rc;
+    *lay = fused_layout(v->n, v->n0);
+    if (v->workspace_bytes < lay->total)
+        return vecchia_set_error(VECCHIA_ENOMEM, "%s: workspace has %zu bytes, needs %zu", who, v->workspace_bytes, lay->total);
     return VECCHIA_OK;
 }
 
@@ -435,5 +453,97 @@ extern "C" int vecchia_backward(const vecchia_view* view, const vecchia_kernel* 
     p.kern = *kern;
     hipError_t e = timed("backward", s, [&] { return launch_backward(p, s); });
     if (e != hipSuccess) return hip_fail(e, "vecchia_backward");
+    return VECCHIA_OK;
+}
+
+extern "C" int vecchia_fused_workspace_bytes(int64_t n, int32_t k, int32_t n0, int32_t precision, size_t* bytes) {
+    if (!bytes) return vecchia_set_error(VECCHIA_EINVAL, "vecchia_fused_workspace_bytes: bytes is NULL");
+    if (k < 1) return vecchia_set_error(VECCHIA_EINVAL, "vecchia_fused_workspace_bytes: need k >= 1");
+    if (k > VECCHIA_KMAX)
+        return vecchia_set_error(VECCHIA_EUNSUPPORTED, "vecchia_fused_workspace_bytes: k=%d exceeds the compiled maximum %d",
+                                 k, VECCHIA_KMAX);
+    if (n < 1 || n0 < 1 || n0 > n) return vecchia_set_error(VECCHIA_EINVAL, "vecchia_fused_workspace_bytes: need 1 <= n0 <= N");
+    if (precision != VECCHIA_FP64 && precision != VECCHIA_FP32)
+        return vecchia_set_error(VECCHIA_EINVAL, "vecchia_fused_workspace_bytes: bad precision");
+    *bytes = fused_layout(n, n0).total;
+    return VECCHIA_OK;
+}
+
+extern "C" int vecchia_forward_fused(const vecchia_view* view, const vecchia_kernel* kern, const void* xi, void* v,
+                                     double* logdet, void* stream) {
+    vecchia_clear_error();
+    FusedLayout lay;
+    int rc = check_fused_view(view, &lay, "vecchia_forward_fused");
+    if (rc) return rc;
+    if ((rc = check_kernel(kern))) return rc;
+    if (!xi || !v) return vecchia_set_error(VECCHIA_EINVAL, "vecchia_forward_fused: xi and v must be set");
+    if (xi == v) return vecchia_set_error(VECCHIA_EINVAL, "vecchia_forward_fused: xi and v must not alias");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* w = static_cast<char*>(view->workspace);
+    double* l0 = reinterpret_cast<double*>(w + lay.l0);
+    double* ld0 = reinterpret_cast<double*>(w + lay.ld0);
+    uint64_t* status = reinterpret_cast<uint64_t*>(w + lay.status);
+    long long* ldfix = reinterpret_cast<long long*>(w + lay.ldfix);
+    hipError_t e = timed("fused_zero", s, [&] { return launch_zero_u64(w + lay.ldpart, 2 * lay.ntiles, s); });
+    if (e != hipSuccess) return hip_fail(e, "vecchia_forward_fused (clear)");
+    e = timed("factor_dense", s, [&] {
+        return launch_factor_dense(view->precision, kern->kind, view->x, view->n0, *kern, l0, ld0, status, s);
+    });
+    if (e != hipSuccess) return hip_fail(e, "vecchia_forward_fused (dense block)");
+    e = timed("forward_dense", s, [&] { return launch_forward_dense(view->precision, l0, view->n0, xi, v, s); });
+    if (e != hipSuccess) return hip_fail(e, "vecchia_forward_fused (dense forward)");
+    FusedLaunch f;
+    f.precision = view->precision;
+    f.kp = view->kp;
+    f.kind = kern->kind;
+    f.n0 = view->n0;
+    f.x = view->x;
+    f.nbr = view->nbr;
+    f.xi = xi;
+    f.v = v;
+    f.ldfix = ldfix;
+    f.status = status;
+    f.diag = kern->sigma * kern->sigma + kern->nugget;
+    f.kern = *kern;
+    const int32_t* lp = view->level_ptr;
+    for (int l = 1; l <= view->n_levels; ++l) {
+        f.s_begin = lp[l] - view->n0;
+        f.s_end = lp[l + 1] - view->n0;
+        if (f.s_end <= f.s_begin) continue;
+        e = timed("forward_fused", s, [&] {
+            switch (view->kp) {
+                case 8: return launch_forward_fused_k8(f, s);
+                case 16: return launch_forward_fused_k16(f, s);
+                case 32: return launch_forward_fused_k32(f, s);
+                case 64: return launch_forward_fused_k64(f, s);
+                default: return hipErrorInvalidValue;
+            }
+        });
+        if (e != hipSuccess) return hip_fail(e, "vecchia_forward_fused (batch)");
+    }
+    if (logdet) {
+        e = timed("logdet", s, [&] {
+            return launch_logdet(reinterpret_cast<double*>(w + lay.ldpart), ldfix, lay.ns > 0 ? lay.ntiles : 0, ld0,
+                                 reinterpret_cast<double*>(w + lay.ldstage), logdet, s);
+        });
+        if (e != hipSuccess) return hip_fail(e, "vecchia_forward_fused (logdet)");
+    }
+    return VECCHIA_OK;
+}
+
+extern "C" int vecchia_fused_status(const vecchia_view* view, void* stream, int64_t* first_bad_slot) {
+    vecchia_clear_error();
+    FusedLayout lay;
+    int rc = check_fused_view(view, &lay, "vecchia_fused_status");
+    if (rc) return rc;
+    uint64_t st[2] = {0, 0};
+    hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    if (e == hipSuccess)
+        e = hipMemcpy(st, static_cast<char*>(view->workspace) + lay.status, sizeof(st), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "vecchia_fused_status");
+    if (first_bad_slot) *first_bad_slot = st[0] == kStatusNone ? -1 : (int64_t)st[0];
+    if (st[0] != kStatusNone)
+        return vecchia_set_error(VECCHIA_ENOTPD, "covariance not positive definite at storage position %llu (%llu points)",
+                                 (unsigned long long)st[0], (unsigned long long)st[1]);
     return VECCHIA_OK;
 }

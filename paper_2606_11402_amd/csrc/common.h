@@ -74,6 +74,35 @@ inline Layout workspace_layout(int64_t n, int kp, int n0, int precision) {
     return w;
 }
 
+// Device workspace of the fused forward (Alg. 1 with nothing stored per
+// point): L0, the per-tile log-sigma sums (ldpart zero, ldfix fixed point,
+// adjacent so that one fill clears both), the logdet staging and the status.
+struct FusedLayout {
+    int64_t ns = 0, ntiles = 0;
+    size_t l0 = 0, ld0 = 0, ldpart = 0, ldfix = 0, ldstage = 0, status = 0, total = 0;
+};
+
+inline FusedLayout fused_layout(int64_t n, int n0) {
+    FusedLayout w;
+    w.ns = n - n0;
+    w.ntiles = w.ns > 0 ? (w.ns + kTile - 1) / kTile : 1;
+    size_t off = 0;
+    w.l0 = off;
+    off = align256(off + (size_t)n0 * n0 * sizeof(double));
+    w.ld0 = off;
+    off = align256(off + sizeof(double));
+    w.ldpart = off;
+    off += (size_t)w.ntiles * sizeof(double);
+    w.ldfix = off;
+    off = align256(off + (size_t)w.ntiles * sizeof(int64_t));
+    w.ldstage = off;
+    off = align256(off + 2 * 256 * sizeof(double));
+    w.status = off;
+    off = align256(off + 8 * sizeof(uint64_t));
+    w.total = off;
+    return w;
+}
+
 // Covariance parameters, pre-scaled on the host.  The e_* constants carry a
 // factor log2(e) so that float kernel values use the hardware exp2; sigma^2
 // enters the float exponential as its base-2 logarithm (one rounding of the
@@ -215,6 +244,8 @@ inline BackwardScratch backward_scratch(int64_t n, int kp, int n0, int precision
 }
 
 constexpr int kLogdetStage = 256;   // first-stage workgroups of the logdet reduction
+// Sets n 64-bit words to zero with a kernel (no memset node if the stream is captured).
+hipError_t launch_zero_u64(void* p, int64_t n, hipStream_t stream);
 // log det = 2 (sum_i (ldpart[i] + 2^-32 ldfix[i]) + ld0), compensated, fixed order.
 hipError_t launch_logdet(const double* ldpart, const long long* ldfix, int64_t nparts, const double* ld0,
                          double* stage, double* out, hipStream_t stream);

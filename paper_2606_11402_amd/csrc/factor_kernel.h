@@ -264,10 +264,18 @@ __device__ __forceinline__ void cholesky_kcc(T* A, double* Dg, T* Inv, int r, bo
 // type TX.  On return the lane holds b for its rows in bv[], the group holds
 // sigma^2 (double), the smallest pivot and whether a pivot or the variance
 // was not positive.
-template <typename T, typename TX, int K, int P, int KIND, bool REFINE>
+//
+// FUSED (Alg. 1 as written, nothing stored): after y = L^-1 k_ci and sigma^2
+// the point gathers its neighbours' values v[c(i)] (type TV), solves
+// w = L^-1 v[c(i)] with the same factor and returns the conditional mean
+// y . w = k_ic K_cc^-1 v[c(i)] = b . v[c(i)] in *mean_out; b itself is never
+// formed (bv[] holds y) and there is no backward substitution.
+template <typename T, typename TX, int K, int P, int KIND, bool REFINE, bool FUSED = false, typename TV = T>
 __device__ __forceinline__ void factor_point(const TX* __restrict__ x, const int32_t* __restrict__ nbr, int n0,
                                              int64_t sp, int r, const Cov<T>& cov, double diag, T* bv,
-                                             double& s2_out, double& minpiv_out, bool& bad_out) {
+                                             double& s2_out, double& minpiv_out, bool& bad_out,
+                                             const TV* vfused = nullptr, double* mean_out = nullptr) {
+    static_assert(!(FUSED && REFINE), "the fused forward has no refinement step");
     constexpr int R = K / P;
     constexpr int NA = P * R * (R + 1) / 2;
     const int64_t base = (sp >> 6) * (int64_t)K * kTile + (sp & 63);
@@ -334,6 +342,24 @@ __device__ __forceinline__ void factor_point(const TX* __restrict__ x, const int
         });
     });
     double s2 = diag - yy;
+    if constexpr (FUSED) {
+        T vc[R];
+        static_for<0, R>([&](auto PI) {
+            constexpr int p = PI;
+            const int32_t j = nbr[base + (int64_t)(p * P + r) * kTile];
+            const TV vj = vfused[j >= 0 ? j : 0];          // unconditional load, selected below
+            vc[p] = j >= 0 ? (T)vj : T(0);
+        });
+        lower_solve<T, K, P>(A, Inv, vc, r);
+        double dot = 0.0;
+        static_for<0, R>([&](auto PI) { dot = fma((double)bv[(int)PI], (double)vc[(int)PI], dot); });
+        *mean_out = group_sum<P>(dot);
+        bad |= !(s2 > 0.0);
+        s2_out = s2;
+        minpiv_out = minpiv;
+        bad_out = bad;
+        return;
+    }
     upper_solve<T, K, P>(A, Inv, bv, r);
 
     if constexpr (REFINE) {

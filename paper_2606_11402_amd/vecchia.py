@@ -328,6 +328,54 @@ class Factor:
         return b, s
 
 
+class FusedForward:
+    """Alg. 1 fused and on the fly: ``vecchia_forward_fused`` recomputes each
+    point's K_cc, factor and conditional mean inside the batch loop and
+    stores no coefficients; the workspace holds only L0, per-tile log-sigma
+    sums and a status word."""
+
+    def __init__(self, dg, kernel, workspace=None):
+        self._lib = _lib.load()
+        self.dg = dg
+        self.kernel = kernel
+        out = ctypes.c_size_t()
+        _lib.check(self._lib.vecchia_fused_workspace_bytes(dg.n, dg.k, dg.n0, dg.precision, ctypes.byref(out)),
+                   "vecchia_fused_workspace_bytes")
+        nbytes = out.value
+        if workspace is None:
+            workspace = torch.empty(nbytes, dtype=torch.uint8, device=dg.device)
+        if workspace.numel() < nbytes or workspace.data_ptr() % 256:
+            raise ValueError("workspace must hold %d bytes, 256-byte aligned" % nbytes)
+        self.workspace = workspace
+        v = _lib.ViewStruct()
+        v.n, v.k, v.kp, v.n0, v.n_levels, v.precision = dg.n, dg.k, dg.kp, dg.n0, dg.n_levels, dg.precision
+        v.x = dg.x.data_ptr()
+        v.nbr = dg.nbr.data_ptr()
+        v.level_ptr = dg.level_ptr.ctypes.data
+        v.workspace = workspace.data_ptr()
+        v.workspace_bytes = workspace.numel()
+        self.view = v
+        self._kc = kernel.to_c()
+
+    def __call__(self, xi, out=None, logdet=None):
+        """v = F(xi) in storage order; if ``logdet`` is a 1-element float64
+        device tensor it receives the log-determinant of the same pass."""
+        if not isinstance(xi, torch.Tensor) or xi.device != self.dg.device or xi.dtype != self.dg.dtype \
+                or xi.numel() != self.dg.n or not xi.is_contiguous():
+            raise ValueError("xi must be a contiguous %s tensor of %d elements" % (self.dg.dtype, self.dg.n))
+        v = torch.empty_like(xi) if out is None else out
+        ld = ctypes.c_void_p(logdet.data_ptr()) if logdet is not None else None
+        _lib.check(self._lib.vecchia_forward_fused(ctypes.byref(self.view), ctypes.byref(self._kc),
+                                                   ctypes.c_void_p(xi.data_ptr()), ctypes.c_void_p(v.data_ptr()), ld,
+                                                   _stream(self.dg.device)), "vecchia_forward_fused")
+        return v
+
+    def status(self):
+        bad = ctypes.c_int64()
+        _lib.check(self._lib.vecchia_fused_status(ctypes.byref(self.view), _stream(self.dg.device), ctypes.byref(bad)),
+                   "vecchia_fused_status")
+
+
 def _align(x):
     return (x + 255) & ~255
 
