@@ -61,10 +61,12 @@ extern "C" {
 #define VECCHIA_N0MAX 128         /* largest dense block (FP64 n0 x n0 in one workgroup's LDS) */
 
 /* ---- covariance ---------------------------------------------------------- */
-/* Stationary kernel kappa(r) of Sec. 2.1 (forms named by the workloads):
- *   kind 0 EXP: sigma^2 exp(-r/ell)
- *   kind 1 M32: sigma^2 (1 + sqrt3 r/ell) exp(-sqrt3 r/ell)
- *   kind 2 SE : sigma^2 exp(-r^2/(2 ell^2))
+/* Stationary kernel kappa(r) of Sec. 2.1 (forms named by the workloads, and
+ * the Matern family with smoothing nu of Fig. 1 at its half-integer members):
+ *   kind 0 EXP: sigma^2 exp(-r/ell)                                (nu = 1/2)
+ *   kind 1 M32: sigma^2 (1 + sqrt3 r/ell) exp(-sqrt3 r/ell)        (nu = 3/2)
+ *   kind 2 SE : sigma^2 exp(-r^2/(2 ell^2))                        (nu -> infinity)
+ *   kind 3 M52: sigma^2 (1 + a + a^2/3) exp(-a), a = sqrt5 r/ell   (nu = 5/2)
  * `nugget` is added only on the diagonal (a point with itself). */
 typedef struct vecchia_kernel {
     int32_t kind;

@@ -27,7 +27,7 @@ headers).  The paper prints no worked numerical example; the figure data
 (batch sizes, KL divergences, timings) are absent, so those quantities are
 "parity unpinned".
 """
-from .covariance import Kernel, EXP, M32, SE, kappa, dkappa_dsigma, dkappa_dell, cov_matrix
+from .covariance import Kernel, EXP, M32, SE, M52, kappa, dkappa_dsigma, dkappa_dell, cov_matrix
 from .tree import tree_order, tree_level, left_child, right_child, parent
 from .graph import Graph, build_graph, preceding_knn, depths, storage_order
 from .vecchia import (Factor, dense_block, conditional, conditional_joint, factor,

@@ -9,21 +9,25 @@ nugget tau added only where the two arguments are the same point (same index):
 
 * EXP: sigma^2 exp(-r/ell)                      (Matern nu = 1/2)
 * M32: sigma^2 (1 + a) exp(-a),  a = sqrt(3) r/ell   (Matern nu = 3/2)
-* SE : sigma^2 exp(-r^2 / (2 ell^2))
+* SE : sigma^2 exp(-r^2 / (2 ell^2))                  (Matern nu -> infinity)
+* M52: sigma^2 (1 + a + a^2/3) exp(-a),  a = sqrt(5) r/ell   (Matern nu = 5/2)
+
+The accuracy study of Fig. 1 uses the Matern family with a smoothing
+parameter nu; the half-integer members have the closed forms above.
 
 Derivatives (nugget excluded): d/dsigma = 2 kappa / sigma and
 d/dell = kappa r/ell^2 (EXP), sigma^2 a^2 exp(-a)/ell (M32),
-kappa r^2/ell^3 (SE).
+kappa r^2/ell^3 (SE), sigma^2 a^2 (1 + a) exp(-a) / (3 ell) (M52).
 
-Pins (tests/test_oracle_covariance.py): EXP and M32 against the general Matern
-form built from scipy.special.kv; SE against scipy.stats.norm.pdf; every
-derivative against a central finite difference.
+Pins (tests/test_oracle_covariance.py): EXP, M32 and M52 against the general
+Matern form built from scipy.special.kv; SE against scipy.stats.norm.pdf;
+every derivative against a central finite difference.
 """
 from dataclasses import dataclass
 
 import numpy as np
 
-EXP, M32, SE = 0, 1, 2
+EXP, M32, SE, M52 = 0, 1, 2, 3
 
 
 @dataclass(frozen=True)
@@ -44,6 +48,9 @@ def kappa(r, kern):
         return s2 * (1.0 + a) * np.exp(-a)
     if kern.kind == SE:
         return s2 * np.exp(-(r * r) / (2.0 * kern.ell * kern.ell))
+    if kern.kind == M52:
+        a = np.sqrt(5.0) * r / kern.ell
+        return s2 * (1.0 + a + a * a / 3.0) * np.exp(-a)
     raise ValueError("unknown kernel kind %r" % (kern.kind,))
 
 
@@ -60,6 +67,9 @@ def dkappa_dell(r, kern):
         return kern.sigma * kern.sigma * a * a * np.exp(-a) / kern.ell
     if kern.kind == SE:
         return kappa(r, kern) * r * r / (kern.ell ** 3)
+    if kern.kind == M52:
+        a = np.sqrt(5.0) * r / kern.ell
+        return kern.sigma * kern.sigma * a * a * (1.0 + a) * np.exp(-a) / (3.0 * kern.ell)
     raise ValueError("unknown kernel kind %r" % (kern.kind,))
 
 

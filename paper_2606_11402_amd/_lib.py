@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(PKG, "libvecchia.so")
 OK, EINVAL, ENOMEM, ENOTPD, EUNSUPPORTED, EHIP, EBUDGET = 0, -1, -2, -3, -4, -5, -6
 FP64, FP32 = 0, 1
 KMAX, N0MAX = 64, 128
-EXP, M32, SE = 0, 1, 2
+EXP, M32, SE, M52 = 0, 1, 2, 3
 
 _NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", ENOTPD: "ENOTPD", EUNSUPPORTED: "EUNSUPPORTED",
           EHIP: "EHIP", EBUDGET: "EBUDGET"}

@@ -20,6 +20,11 @@ __device__ __forceinline__ void cov_and_dell(double r2, const Cov<double>& c, do
         const double e = exp(-a);
         kap = c.s2 * (1.0 + a) * e;
         dell = c.s2 * a * a * e * c.inv_ell;
+    } else if constexpr (KIND == 3) {
+        const double a = sqrt(r2) * c.c_m52;
+        const double e = exp(-a);
+        kap = c.s2 * fma(a, fma(a, 1.0 / 3.0, 1.0), 1.0) * e;
+        dell = c.s2 * a * a * (1.0 + a) * e * c.inv_ell * (1.0 / 3.0);
     } else {
         kap = c.s2 * exp(r2 * c.c_se);
         dell = kap * r2 * c.inv_ell * c.inv_ell * c.inv_ell;

@@ -335,6 +335,7 @@ static hipError_t backward_kind(const BackwardLaunch& p, hipStream_t s) {
         case 0: return backward_t<TS, KP, 0>(p, s);
         case 1: return backward_t<TS, KP, 1>(p, s);
         case 2: return backward_t<TS, KP, 2>(p, s);
+        case 3: return backward_t<TS, KP, 3>(p, s);
         default: return hipErrorInvalidValue;
     }
 }

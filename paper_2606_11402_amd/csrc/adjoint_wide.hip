@@ -95,6 +95,7 @@ hipError_t launch_adj_theta_wide(const AdjArgs<TS>& a, int kind, hipStream_t s) 
         case 0: hipLaunchKernelGGL((adj_theta_wide_kernel<TS, 0>), dim3((unsigned)a.nblocks), dim3(kBlock), 0, s, a); break;
         case 1: hipLaunchKernelGGL((adj_theta_wide_kernel<TS, 1>), dim3((unsigned)a.nblocks), dim3(kBlock), 0, s, a); break;
         case 2: hipLaunchKernelGGL((adj_theta_wide_kernel<TS, 2>), dim3((unsigned)a.nblocks), dim3(kBlock), 0, s, a); break;
+        case 3: hipLaunchKernelGGL((adj_theta_wide_kernel<TS, 3>), dim3((unsigned)a.nblocks), dim3(kBlock), 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -77,7 +77,7 @@ int hip_fail(hipError_t e, const char* where) {
 
 int check_kernel(const vecchia_kernel* k) {
     if (!k) return vecchia_set_error(VECCHIA_EINVAL, "kernel is NULL");
-    if (k->kind < 0 || k->kind > 2) return vecchia_set_error(VECCHIA_EINVAL, "kernel kind %d not in {0,1,2}", k->kind);
+    if (k->kind < 0 || k->kind > 3) return vecchia_set_error(VECCHIA_EINVAL, "kernel kind %d not in {0,1,2,3}", k->kind);
     if (!(k->sigma > 0.0) || !std::isfinite(k->sigma)) return vecchia_set_error(VECCHIA_EINVAL, "kernel sigma must be > 0");
     if (!(k->ell > 0.0) || !std::isfinite(k->ell)) return vecchia_set_error(VECCHIA_EINVAL, "kernel ell must be > 0");
     if (!(k->nugget >= 0.0) || !std::isfinite(k->nugget)) return vecchia_set_error(VECCHIA_EINVAL, "kernel nugget must be >= 0");

@@ -115,9 +115,11 @@ struct Cov {
     T m32_lin;     // -ln(2) sigma^2: sigma^2 (1 + a) = sigma^2 + m32_lin * (-a log2(e))
     T inv_ell;     // 1/ell
     T c_m32;       // sqrt(3)/ell
+    T c_m52;       // sqrt(5)/ell
     T c_se;        // -1/(2 ell^2)
     T e_exp;       // -log2(e)/ell
     T e_m32;       // -sqrt(3) log2(e)/ell
+    T e_m52;       // -sqrt(5) log2(e)/ell
     T e_se;        // -log2(e)/(2 ell^2)
 };
 
@@ -131,9 +133,11 @@ inline Cov<T> make_cov(const vecchia_kernel& k) {
     c.m32_lin = (T)(-0.6931471805599453 * k.sigma * k.sigma);
     c.inv_ell = (T)(1.0 / k.ell);
     c.c_m32 = (T)(sqrt3 / k.ell);
+    c.c_m52 = (T)(2.23606797749979 / k.ell);
     c.c_se = (T)(-0.5 / (k.ell * k.ell));
     c.e_exp = (T)(-log2e / k.ell);
     c.e_m32 = (T)(-sqrt3 * log2e / k.ell);
+    c.e_m52 = (T)(-2.23606797749979 * log2e / k.ell);
     c.e_se = (T)(-0.5 * log2e / (k.ell * k.ell));
     return c;
 }
@@ -155,6 +159,11 @@ __device__ __forceinline__ float cov_r2(float r2, const Cov<float>& c) {
     } else if constexpr (KIND == 1) {
         const float t = __builtin_amdgcn_sqrtf(r2) * c.e_m32;            // -a log2(e)
         return __builtin_fmaf(t, c.m32_lin, c.s2) * __builtin_amdgcn_exp2f(t);
+    } else if constexpr (KIND == 3) {
+        const float r = __builtin_amdgcn_sqrtf(r2);
+        const float a = r * c.c_m52;                                      // sqrt(5) r / ell
+        const float poly = __builtin_fmaf(a, __builtin_fmaf(a, 1.0f / 3.0f, 1.0f), 1.0f);
+        return c.s2 * poly * __builtin_amdgcn_exp2f(r * c.e_m52);
     } else {
         return __builtin_amdgcn_exp2f(__builtin_fmaf(r2, c.e_se, c.ls2));
     }
@@ -167,6 +176,9 @@ __device__ __forceinline__ double cov_r2(double r2, const Cov<double>& c) {
     } else if constexpr (KIND == 1) {
         const double a = sqrt(r2) * c.c_m32;
         return c.s2 * (1.0 + a) * exp(-a);
+    } else if constexpr (KIND == 3) {
+        const double a = sqrt(r2) * c.c_m52;
+        return c.s2 * fma(a, fma(a, 1.0 / 3.0, 1.0), 1.0) * exp(-a);
     } else {
         return c.s2 * exp(r2 * c.c_se);
     }

@@ -56,6 +56,7 @@ static hipError_t launch_wide_t(const FusedLaunch& L, hipStream_t s) {
         case 0: hipLaunchKernelGGL((forward_fused_wide_kernel<TS, 0>), dim3((unsigned)a.nblocks), dim3(kBlock), 0, s, a, cov); break;
         case 1: hipLaunchKernelGGL((forward_fused_wide_kernel<TS, 1>), dim3((unsigned)a.nblocks), dim3(kBlock), 0, s, a, cov); break;
         case 2: hipLaunchKernelGGL((forward_fused_wide_kernel<TS, 2>), dim3((unsigned)a.nblocks), dim3(kBlock), 0, s, a, cov); break;
+        case 3: hipLaunchKernelGGL((forward_fused_wide_kernel<TS, 3>), dim3((unsigned)a.nblocks), dim3(kBlock), 0, s, a, cov); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

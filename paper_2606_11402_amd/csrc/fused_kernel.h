@@ -68,6 +68,7 @@ hipError_t launch_forward_fused_t(int kind, const FusedArgs<TS>& args, const vec
         case 0: hipLaunchKernelGGL((forward_fused_kernel<TS, K, 0>), dim3((unsigned)a.nblocks), dim3(kBlock), 0, s, a, cov); break;
         case 1: hipLaunchKernelGGL((forward_fused_kernel<TS, K, 1>), dim3((unsigned)a.nblocks), dim3(kBlock), 0, s, a, cov); break;
         case 2: hipLaunchKernelGGL((forward_fused_kernel<TS, K, 2>), dim3((unsigned)a.nblocks), dim3(kBlock), 0, s, a, cov); break;
+        case 3: hipLaunchKernelGGL((forward_fused_kernel<TS, K, 3>), dim3((unsigned)a.nblocks), dim3(kBlock), 0, s, a, cov); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -379,7 +379,7 @@ extern "C" int serve_submit(vecchia_server* s, const double* x, int64_t n, int32
     if (kp < 0 || n < 1 || n >= (int64_t(1) << 31) || n0 < 1 || n0 > n)
         return vecchia_set_error(VECCHIA_EINVAL, "serve_submit: need 1 <= k <= %d and 1 <= n0 <= min(N, %d)",
                                  VECCHIA_KMAX, VECCHIA_N0MAX);
-    if (kern->kind < 0 || kern->kind > 2 || !(kern->sigma > 0) || !(kern->ell > 0) || !(kern->nugget >= 0))
+    if (kern->kind < 0 || kern->kind > 3 || !(kern->sigma > 0) || !(kern->ell > 0) || !(kern->nugget >= 0))
         return vecchia_set_error(VECCHIA_EINVAL, "serve_submit: bad kernel parameters");
     const Footprint fp = footprint(n, kp, n0, n - n0);   // exact size once the graph is built
     std::unique_ptr<Request> r(new Request());

@@ -14,7 +14,7 @@ import torch
 
 from . import _lib
 
-EXP, M32, SE = _lib.EXP, _lib.M32, _lib.SE
+EXP, M32, SE, M52 = _lib.EXP, _lib.M32, _lib.SE, _lib.M52
 FP64, FP32 = _lib.FP64, _lib.FP32
 _TORCH_DTYPE = {FP64: torch.float64, FP32: torch.float32}
 _NP_DTYPE = {FP64: np.float64, FP32: np.float32}

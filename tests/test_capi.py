@@ -103,7 +103,7 @@ def test_kernel_validation():
     v.x = v.nbr = v.workspace = 256
     v.level_ptr = lp.ctypes.data
     v.workspace_bytes = 1 << 30
-    for bad in (_lib.KernelStruct(3, 1.0, 0.1, 0.0), _lib.KernelStruct(0, -1.0, 0.1, 0.0),
+    for bad in (_lib.KernelStruct(4, 1.0, 0.1, 0.0), _lib.KernelStruct(0, -1.0, 0.1, 0.0),
                 _lib.KernelStruct(0, 1.0, 0.0, 0.0), _lib.KernelStruct(0, 1.0, 0.1, -1e-3)):
         assert lib.vecchia_factor(ctypes.byref(v), ctypes.byref(bad), None) == _lib.EINVAL
 

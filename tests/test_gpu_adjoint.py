@@ -9,7 +9,7 @@ import torch
 
 import oracle
 import workloads
-from oracle import Kernel, EXP, M32, SE
+from oracle import Kernel, EXP, M32, SE, M52
 from paper_2606_11402_amd import FP32, FP64, Factor, Graph, KernelParams
 from paper_2606_11402_amd import autograd as vag
 from gpu_helpers import rel_err
@@ -48,7 +48,7 @@ def theta_err(a, ref):
     return float(np.max(np.abs(np.asarray(a) - ref) / np.abs(ref)))
 
 
-@pytest.mark.parametrize("kind", [EXP, M32, SE])
+@pytest.mark.parametrize("kind", [EXP, M32, SE, M52])
 @pytest.mark.parametrize("k", [8, 16, 32, 64])
 def test_forward_vjp_fp64(kind, k):
     c = Case(900 + 3 * k, k, 48, Kernel(kind, 1.2, 0.2, 1e-5 if kind == SE else 0.0), FP64, 200 + k)

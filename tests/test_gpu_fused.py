@@ -9,7 +9,7 @@ import torch
 
 import oracle
 import workloads
-from oracle import Kernel, EXP, M32, SE
+from oracle import Kernel, EXP, M32, SE, M52
 from paper_2606_11402_amd import FP32, FP64, Factor, FusedForward, Graph, KernelParams, VecchiaError
 from gpu_helpers import rel_err
 
@@ -57,7 +57,7 @@ def against_oracle(x, k, n0, kern, precision, xi_in):
     return errs
 
 
-@pytest.mark.parametrize("kind", [EXP, M32, SE])
+@pytest.mark.parametrize("kind", [EXP, M32, SE, M52])
 @pytest.mark.parametrize("k", [5, 8, 16, 32, 64])
 def test_fused_forward_fp64(kind, k):
     n = 1700 + 11 * k                      # ragged last tile

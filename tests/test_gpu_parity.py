@@ -16,7 +16,7 @@ import torch
 
 import oracle
 import workloads
-from oracle import Kernel, EXP, M32, SE
+from oracle import Kernel, EXP, M32, SE, M52
 from paper_2606_11402_amd import FP32, FP64, VecchiaError
 from gpu_helpers import Run, b_backward_error, check_capped, oracle_run, rel_err
 
@@ -125,7 +125,7 @@ def test_exact_limit_dense_cholesky_fp64(n):
     assert rel_err(s, np.diag(l)[1:]) <= 1e-10
 
 
-@pytest.mark.parametrize("kind", [EXP, M32, SE])
+@pytest.mark.parametrize("kind", [EXP, M32, SE, M52])
 @pytest.mark.parametrize("k", [5, 8, 12, 16, 20, 32, 48, 64])
 def test_kernels_and_widths_fp64(kind, k):
     n = 1500 + 7 * k                          # ragged last tile
@@ -134,7 +134,7 @@ def test_kernels_and_widths_fp64(kind, k):
     check_against_oracle(x, k, 64, kern, FP64, workloads.white_noise(n, 130 + k), caps=CAPS_FP64_WIDTHS.get((kind, k)))
 
 
-@pytest.mark.parametrize("kind", [EXP, M32, SE])
+@pytest.mark.parametrize("kind", [EXP, M32, SE, M52])
 @pytest.mark.parametrize("k", [8, 16, 32, 64])
 def test_kernels_and_widths_fp32(kind, k):
     n = 3000 + 13 * k

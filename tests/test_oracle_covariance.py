@@ -5,7 +5,7 @@ import scipy.special
 import scipy.stats
 
 import oracle
-from oracle import Kernel, EXP, M32, SE
+from oracle import Kernel, EXP, M32, SE, M52
 
 
 def matern_general(r, nu, sigma, ell):
@@ -27,13 +27,19 @@ def test_m32_is_matern_three_halves():
     np.testing.assert_allclose(oracle.kappa(R, k), matern_general(R, 1.5, 0.7, 0.05), rtol=1e-10)
 
 
+def test_m52_is_matern_five_halves():
+    k = Kernel(M52, sigma=1.2, ell=0.08)
+    np.testing.assert_allclose(oracle.kappa(R, k), matern_general(R, 2.5, 1.2, 0.08), rtol=1e-10)
+    assert oracle.kappa(0.0, k) == pytest.approx(1.44, rel=1e-15)      # kappa(0) = sigma^2
+
+
 def test_se_is_scaled_normal_pdf():
     k = Kernel(SE, sigma=2.0, ell=0.3)
     ref = 4.0 * scipy.stats.norm.pdf(R, scale=0.3) * 0.3 * np.sqrt(2.0 * np.pi)
     np.testing.assert_allclose(oracle.kappa(R, k), ref, rtol=1e-13)
 
 
-@pytest.mark.parametrize("kind", [EXP, M32, SE])
+@pytest.mark.parametrize("kind", [EXP, M32, SE, M52])
 def test_derivatives_central_difference(kind):
     h = 1e-6
     k = Kernel(kind, sigma=1.1, ell=0.15)
