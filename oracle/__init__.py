@@ -20,6 +20,9 @@ Gaussian Processes with Vecchia's Approximation):
                     building blocks in the abstract.
 * ``adjoint``    -- kernel-parameter and white-noise derivatives (Sec. 2.3),
                     written as closed forms of the conditional formulas.
+* ``tangent``    -- the forward-mode counterparts (Sec. 2.3: forward and
+                    backward derivatives), same closed forms differentiated
+                    in a direction.
 
 Parity status: every function here is pinned by ``tests/test_oracle_*.py``
 against closed forms, library routines or brute force (see the module
@@ -35,11 +38,13 @@ from .vecchia import (Factor, dense_block, conditional, conditional_joint, facto
                       logdet, dense_covariance)
 from .adjoint import forward_vjp, inverse_vjp, logdet_vjp, theta_grad
 
+from .tangent import factor_tangent, forward_jvp
+
 __all__ = [
     "Kernel", "EXP", "M32", "SE", "kappa", "dkappa_dsigma", "dkappa_dell", "cov_matrix",
     "tree_order", "tree_level", "left_child", "right_child", "parent",
     "Graph", "build_graph", "preceding_knn", "depths", "storage_order",
     "Factor", "dense_block", "conditional", "conditional_joint", "factor", "forward",
     "forward_sequential", "forward_sparse_solve", "inverse", "logdet", "dense_covariance",
-    "forward_vjp", "inverse_vjp", "logdet_vjp", "theta_grad",
+    "forward_vjp", "inverse_vjp", "logdet_vjp", "theta_grad", "factor_tangent", "forward_jvp",
 ]
