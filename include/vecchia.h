@@ -249,6 +249,28 @@ int vecchia_backward_noalloc(const vecchia_view* view, const vecchia_kernel* ker
                              const void* xi, const void* v, const void* v_bar, const void* xi_bar_in,
                              double logdet_bar, void* xi_bar, void* v_bar_out, double* theta_bar, void* stream);
 
+/* Forward-mode derivatives (Sec. 2.3: forward and backward derivatives with
+ * respect to the kernel parameters): the tangent of v = F(xi; sigma, ell) and
+ * of the logdet in the direction (xi_dot, sigma_dot, ell_dot),
+ *     v_dot = F(xi_dot) + (dF/dsigma sigma_dot + dF/dell ell_dot) xi.
+ * Per sparse point, with K_dot = sigma_dot dK/dsigma + ell_dot dK/dell
+ * (nugget excluded) and the stored b, sigma:
+ *     b_dot = K_cc^-1 (k_dot_ci - K_dot_cc b),
+ *     sigma_dot_i = (K_dot_ii - 2 k_dot_ci . b + b . K_dot_cc b) / (2 sigma_i),
+ * then batch by batch v_dot_i = b_dot . v[c(i)] + b . v_dot[c(i)] +
+ * sigma_dot_i xi_i + sigma_i xi_dot_i; the dense block uses the Cholesky
+ * tangent L0_dot = L0 Phi(L0^-1 K0_dot L0^-T).  K_cc is recomputed per point
+ * (double arithmetic).  xi and v (device, N, storage order) are the forward
+ * pair of the factored view; xi_dot may be NULL (zero); v_dot (device, N)
+ * receives the tangent; logdet_dot (device, 1 double, nullable) receives
+ * 2 sum sigma_dot_i / sigma_i + tr(K0^-1 K0_dot).  scratch: device buffer of
+ * vecchia_jvp_scratch_bytes() bytes, 256-byte aligned.  Errors: EINVAL,
+ * ENOMEM (scratch too small), EHIP. */
+int vecchia_jvp_scratch_bytes(const vecchia_view* view, size_t* bytes);
+int vecchia_forward_jvp(const vecchia_view* view, const vecchia_kernel* kern, const void* xi, const void* v,
+                        const void* xi_dot, double sigma_dot, double ell_dot, void* v_dot, double* logdet_dot,
+                        void* scratch, size_t scratch_bytes, void* stream);
+
 /* Synchronises `stream`, then reports how many points of the last
  * vecchia_factor had a non-positive pivot or variance (not_pd) and, for
  * VECCHIA_FP32, how many were recomputed in double (recomputed). */

@@ -75,6 +75,9 @@ _SIGNATURES = {
     "vecchia_fused_workspace_bytes": (c_int32, [c_int64, c_int32, c_int32, c_int32, P(c_size_t)]),
     "vecchia_forward_fused": (c_int32, [P(ViewStruct), P(KernelStruct), c_void_p, c_void_p, c_void_p, c_void_p]),
     "vecchia_fused_status": (c_int32, [P(ViewStruct), c_void_p, P(c_int64)]),
+    "vecchia_jvp_scratch_bytes": (c_int32, [P(ViewStruct), P(c_size_t)]),
+    "vecchia_forward_jvp": (c_int32, [P(ViewStruct), P(KernelStruct), c_void_p, c_void_p, c_void_p, c_double, c_double,
+                                      c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "vecchia_status": (c_int32, [P(ViewStruct), c_void_p, P(c_int64)]),
     "vecchia_factor_counts": (c_int32, [P(ViewStruct), c_void_p, P(c_int64), P(c_int64)]),
     "vecchia_padded_k": (c_int32, [c_int32]),

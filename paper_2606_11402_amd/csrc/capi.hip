@@ -9,6 +9,7 @@
 #include "apply.h"
 #include "fused_kernel.h"
 #include "status.h"
+#include "tangent.h"
 
 using namespace vk;
 
@@ -545,5 +546,72 @@ extern "C" int vecchia_fused_status(const vecchia_view* view, void* stream, int6
     if (st[0] != kStatusNone)
         return vecchia_set_error(VECCHIA_ENOTPD, "covariance not positive definite at storage position %llu (%llu points)",
                                  (unsigned long long)st[0], (unsigned long long)st[1]);
+    return VECCHIA_OK;
+}
+
+extern "C" int vecchia_jvp_scratch_bytes(const vecchia_view* view, size_t* bytes) {
+    vecchia_clear_error();
+    Layout lay;
+    int rc = check_view(view, &lay, "vecchia_jvp_scratch_bytes");
+    if (rc) return rc;
+    if (!bytes) return vecchia_set_error(VECCHIA_EINVAL, "vecchia_jvp_scratch_bytes: bytes is NULL");
+    *bytes = tangent_scratch(view->n, view->kp, view->n0, view->precision).total;
+    return VECCHIA_OK;
+}
+
+extern "C" int vecchia_forward_jvp(const vecchia_view* view, const vecchia_kernel* kern, const void* xi, const void* v,
+                                   const void* xi_dot, double sigma_dot, double ell_dot, void* v_dot,
+                                   double* logdet_dot, void* scratch, size_t scratch_bytes, void* stream) {
+    vecchia_clear_error();
+    Layout lay;
+    int rc = check_view(view, &lay, "vecchia_forward_jvp");
+    if (rc) return rc;
+    if ((rc = check_kernel(kern))) return rc;
+    if (!xi || !v || !v_dot || !scratch)
+        return vecchia_set_error(VECCHIA_EINVAL, "vecchia_forward_jvp: xi, v, v_dot and scratch must be set");
+    if (v_dot == v || v_dot == xi || (xi_dot && v_dot == xi_dot))
+        return vecchia_set_error(VECCHIA_EINVAL, "vecchia_forward_jvp: v_dot must not alias an input");
+    if (!std::isfinite(sigma_dot) || !std::isfinite(ell_dot))
+        return vecchia_set_error(VECCHIA_EINVAL, "vecchia_forward_jvp: the direction must be finite");
+    const TangentScratch sc = tangent_scratch(view->n, view->kp, view->n0, view->precision);
+    if (scratch_bytes < sc.total)
+        return vecchia_set_error(VECCHIA_ENOMEM, "vecchia_forward_jvp: scratch has %zu bytes, needs %zu", scratch_bytes,
+                                 sc.total);
+    if (reinterpret_cast<uintptr_t>(scratch) & 255)
+        return vecchia_set_error(VECCHIA_EINVAL, "vecchia_forward_jvp: scratch must be 256-byte aligned");
+    char* sb = static_cast<char*>(scratch);
+    TangentLaunch t;
+    t.precision = view->precision;
+    t.kp = view->kp;
+    t.kind = kern->kind;
+    t.n0 = view->n0;
+    t.n_levels = view->n_levels;
+    t.n = view->n;
+    t.ns = lay.ns;
+    t.level_ptr = view->level_ptr;
+    t.x = view->x;
+    t.b = ws<char>(view, lay.b);
+    t.sigma = ws<char>(view, lay.sigma);
+    t.xi = xi;
+    t.v = v;
+    t.xi_dot = xi_dot;
+    t.nbr = view->nbr;
+    t.l0 = ws<double>(view, lay.l0);
+    t.bdot = sb + sc.bdot;
+    t.sigdot = sb + sc.sigdot;
+    t.v_dot = v_dot;
+    t.part = reinterpret_cast<double*>(sb + sc.part);
+    t.fixzero = reinterpret_cast<double*>(sb + sc.fixzero);
+    t.ld0dot = reinterpret_cast<double*>(sb + sc.ld0dot);
+    t.stage = reinterpret_cast<double*>(sb + sc.stage);
+    t.logdet_dot = logdet_dot;
+    t.diag = kern->sigma * kern->sigma + kern->nugget;
+    t.sigma_amp = kern->sigma;
+    t.sdot = sigma_dot;
+    t.ldot = ell_dot;
+    t.kern = *kern;
+    hipError_t e = timed("forward_jvp", static_cast<hipStream_t>(stream),
+                         [&] { return launch_forward_tangent(t, static_cast<hipStream_t>(stream)); });
+    if (e != hipSuccess) return hip_fail(e, "vecchia_forward_jvp");
     return VECCHIA_OK;
 }

@@ -277,6 +277,27 @@ class Factor:
                    "vecchia_backward")
         return xi_bar, v_bar_out, theta
 
+    def jvp(self, xi, v, xi_dot=None, sigma_dot=0.0, ell_dot=0.0, logdet=True, scratch=None):
+        """Forward-mode derivative: (v_dot, logdet_dot or None) of v = F(xi)
+        and of the logdet in the direction (xi_dot, sigma_dot, ell_dot); (xi,
+        v) is the forward pair of this factor."""
+        xi = self._vec(xi, "xi")
+        v = self._vec(v, "v")
+        xd = self._vec(xi_dot, "xi_dot") if xi_dot is not None else None
+        v_dot = torch.empty_like(v)
+        ld = torch.empty(1, dtype=torch.float64, device=self.dg.device) if logdet else None
+        nbytes = ctypes.c_size_t()
+        _lib.check(self._lib.vecchia_jvp_scratch_bytes(ctypes.byref(self.view), ctypes.byref(nbytes)),
+                   "vecchia_jvp_scratch_bytes")
+        if scratch is None or scratch.numel() < nbytes.value:
+            scratch = torch.empty(nbytes.value, dtype=torch.uint8, device=self.dg.device)
+        ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+        _lib.check(self._lib.vecchia_forward_jvp(ctypes.byref(self.view), ctypes.byref(self._kc), ptr(xi), ptr(v),
+                                                 ptr(xd), float(sigma_dot), float(ell_dot), ptr(v_dot), ptr(ld),
+                                                 ptr(scratch), scratch.numel(), _stream(self.dg.device)),
+                   "vecchia_forward_jvp")
+        return v_dot, ld
+
     def counts(self):
         """(points with a non-positive pivot or variance, points recomputed in
         double on the FP32 path) of the last factorisation; synchronises."""
