@@ -153,6 +153,8 @@ def main():
     ap.add_argument("--n", type=int, default=None, help="override N (default: the workload's)")
     ap.add_argument("--k", type=int, default=None)
     ap.add_argument("--threads", type=int, default=0, help="host threads for the graph build")
+    ap.add_argument("--host-knn", action="store_true",
+                    help="run the graph's neighbour search on the host instead of the device")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the sampled oracle check")
     ap.add_argument("--cpu-sample", type=int, default=16384)
@@ -200,9 +202,13 @@ def main():
     xi_in = w.xi(n)
     log("points ready in %.1fs; building graph on the host" % (time.time() - t))
     t = time.time()
-    g = Graph(x, k, n0, n_threads=args.threads)
+    g = Graph(x, k, n0, n_threads=args.threads, knn_device=None if args.host_knn else "cuda:0")
     graph_s = time.time() - t
-    log("graph: %.1fs %s, %d levels" % (graph_s, {a: round(b, 2) for a, b in g.build_times().items()}, g.n_levels))
+    graph_phases = {a: round(b, 2) for a, b in g.build_times().items()}
+    if g.knn_seconds is not None:
+        graph_phases["neighbours"] = round(g.knn_seconds, 2)      # device search incl. transfers
+    log("graph: %.1fs %s, %d levels (neighbour search on the %s)" % (graph_s, graph_phases, g.n_levels,
+                                                                      "host" if args.host_knn else "device"))
     t = time.time()
     dg = g.to_device(precision, dev)
     dt = dg.dtype
@@ -351,7 +357,8 @@ def main():
                    "factor_redo": round(redo_ms, 4), "forward": round(fwd_ms, 4), "forward_levels_only": round(levels_ms, 4),
                    "logdet": round(ld_ms, 4), "inverse": round(inv_ms, 4),
                    "instrumented_step_ms": round((tp1 - tp0) * 1e3 / steps, 3)},
-        "graph_build_s": round(graph_s, 2), "graph_phases_s": {a: round(b, 2) for a, b in g.build_times().items()},
+        "graph_build_s": round(graph_s, 2), "graph_phases_s": graph_phases,
+        "graph_neighbour_search": "host" if args.host_knn else "device (graph_knn_device, incl. transfers)",
         "fused_forward": fused,
     }
 

@@ -93,6 +93,33 @@ typedef struct vecchia_graph vecchia_graph;   /* opaque, owned by the library */
 int graph_build(const double* x, int64_t n, int32_t d, int32_t k, int32_t n0,
                 int32_t n_threads, vecchia_graph** out);
 
+/* The same build with its neighbour search on the device (the preceding
+ * k-NN query of Sec. 2.3's last paragraph), in three steps:
+ *   graph_build_begin  orders the points (tree, as graph_build) and leaves the
+ *                      graph pending; same arguments and errors as graph_build;
+ *   graph_knn_nodes    exports the query tree for the device: nodes (host,
+ *                      N * VECCHIA_KNN_NODE_BYTES bytes, in-order layout; the
+ *                      caller copies them to the device) and rank_of (host,
+ *                      N int32: tree slot -> node index);
+ *   graph_knn_device   (device, enqueued on `stream`) writes rows (device,
+ *                      (N - n0) x k int32, row r for tree slot n0 + r): the k
+ *                      slots j < slot with the smallest (D, j), ascending,
+ *                      -1 padded -- the rows graph_build computes on the host,
+ *                      bit for bit;
+ *   graph_build_finish takes the rows back (host, same layout), checks that
+ *                      every entry names a preceding slot and that each row
+ *                      ascends by (distance, slot) (EINVAL otherwise), then
+ *                      computes depths and the storage order.
+ * Until graph_build_finish succeeds, graph_export, graph_export_nbr and
+ * graph_export_children return EINVAL.  Device buffers are the caller's. */
+#define VECCHIA_KNN_NODE_BYTES 40
+int graph_build_begin(const double* x, int64_t n, int32_t d, int32_t k, int32_t n0,
+                      int32_t n_threads, vecchia_graph** out);
+int graph_knn_nodes(const vecchia_graph* g, void* nodes, int32_t* rank_of);
+int graph_knn_device(const void* nodes, const int32_t* rank_of, int64_t n, int32_t d, int32_t k, int32_t n0,
+                     int32_t* rows, void* stream);
+int graph_build_finish(vecchia_graph* g, const int32_t* rows);
+
 /* Sizes of a built graph (any pointer may be NULL).  kp = padded width of the
  * tiled layout; n_levels = number of sparse batches L. */
 int graph_info(const vecchia_graph* g, int64_t* n, int32_t* d, int32_t* k, int32_t* kp,

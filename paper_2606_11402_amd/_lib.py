@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(PKG, "libvecchia.so")
 OK, EINVAL, ENOMEM, ENOTPD, EUNSUPPORTED, EHIP, EBUDGET = 0, -1, -2, -3, -4, -5, -6
 FP64, FP32 = 0, 1
 KMAX, N0MAX = 64, 128
+KNN_NODE_BYTES = 40
 EXP, M32, SE, M52 = 0, 1, 2, 3
 
 _NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", ENOTPD: "ENOTPD", EUNSUPPORTED: "EUNSUPPORTED",
@@ -54,6 +55,10 @@ class ViewStruct(ctypes.Structure):
 
 _SIGNATURES = {
     "graph_build": (c_int32, [P(c_double), c_int64, c_int32, c_int32, c_int32, c_int32, P(c_void_p)]),
+    "graph_build_begin": (c_int32, [P(c_double), c_int64, c_int32, c_int32, c_int32, c_int32, P(c_void_p)]),
+    "graph_knn_nodes": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "graph_knn_device": (c_int32, [c_void_p, c_void_p, c_int64, c_int32, c_int32, c_int32, c_void_p, c_void_p]),
+    "graph_build_finish": (c_int32, [c_void_p, c_void_p]),
     "graph_info": (c_int32, [c_void_p, P(c_int64), P(c_int32), P(c_int32), P(c_int32), P(c_int32), P(c_int32)]),
     "graph_export": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "graph_export_nbr": (c_int32, [c_void_p, c_int32, c_void_p]),

@@ -35,6 +35,7 @@
 #include <thread>
 #include <vector>
 
+#include "knn.h"
 #include "status.h"
 #include "vecchia.h"
 
@@ -54,6 +55,7 @@ struct vecchia_graph {
     std::vector<int32_t> level_ptr;    // n_levels + 2
     int nthreads = 1;                  // host threads of the build, reused by the exports
     double times[4] = {0, 0, 0, 0};
+    bool pending = false;              // begun (tree only): neighbours, depths and storage still missing
 };
 
 namespace {
@@ -314,7 +316,6 @@ void query_preceding(const vecchia_graph& g, const QNode* nodes, int64_t i, int3
 
 void build_neighbours(vecchia_graph& g, int nthreads) {
     const int64_t n = g.n, ns = g.n - g.n0;
-    inorder(g);
     std::vector<QNode> nodes(n);
     parallel_for(n, 1 << 16, nthreads, [&](int64_t a, int64_t b) {
         for (int64_t r = a; r < b; ++r) {
@@ -428,47 +429,162 @@ void device_row(const vecchia_graph& g, int64_t sp, int32_t* out) {
 
 }  // namespace
 
+namespace {
+
+int check_build_args(const double* x, int64_t n, int32_t d, int32_t k, int32_t n0, vecchia_graph** out,
+                     const char* who) {
+    if (!out) return vecchia_set_error(VECCHIA_EINVAL, "%s: out is NULL", who);
+    *out = nullptr;
+    if (!x) return vecchia_set_error(VECCHIA_EINVAL, "%s: x is NULL", who);
+    if (n < 1 || n >= (int64_t(1) << 31)) return vecchia_set_error(VECCHIA_EINVAL, "%s: need 1 <= N < 2^31, got %lld", who, (long long)n);
+    if (d < 1 || d > 3) return vecchia_set_error(VECCHIA_EINVAL, "%s: need 1 <= d <= 3, got %d", who, d);
+    if (k < 1) return vecchia_set_error(VECCHIA_EINVAL, "%s: need k >= 1, got %d", who, k);
+    if (k > VECCHIA_KMAX)
+        return vecchia_set_error(VECCHIA_EUNSUPPORTED, "%s: k=%d exceeds the compiled maximum %d", who, k, VECCHIA_KMAX);
+    if (n0 < 1 || n0 > n) return vecchia_set_error(VECCHIA_EINVAL, "%s: need 1 <= n0 <= N, got n0=%d", who, n0);
+    for (int64_t i = 0; i < n * d; ++i)
+        if (!std::isfinite(x[i])) return vecchia_set_error(VECCHIA_EINVAL, "%s: non-finite coordinate at point %lld", who, (long long)(i / d));
+    return VECCHIA_OK;
+}
+
+// Tree order and in-order sequence (the part that the neighbour search,
+// wherever it runs, needs first).
+vecchia_graph* begin_graph(const double* x, int64_t n, int32_t d, int32_t k, int32_t n0, int nthreads) {
+    vecchia_graph* g = new vecchia_graph();
+    g->n = n;
+    g->d = d;
+    g->k = k;
+    g->kp = vecchia_padded_k(k);
+    g->n0 = n0;
+    g->nthreads = nthreads;
+    auto t0 = std::chrono::steady_clock::now();
+    build_tree(*g, x, nthreads);
+    inorder(*g);
+    g->times[0] = seconds_since(t0);
+    return g;
+}
+
+void finish_graph(vecchia_graph& g) {
+    auto t0 = std::chrono::steady_clock::now();
+    build_depth(g, g.nthreads);
+    g.times[2] = seconds_since(t0);
+    t0 = std::chrono::steady_clock::now();
+    build_storage(g);
+    g.times[3] = seconds_since(t0);
+    g.pending = false;
+}
+
+int threads_of(int32_t n_threads) {
+    return n_threads > 0 ? n_threads : (int)std::max(1u, std::thread::hardware_concurrency());
+}
+
+}  // namespace
+
 extern "C" int graph_build(const double* x, int64_t n, int32_t d, int32_t k, int32_t n0, int32_t n_threads,
                            vecchia_graph** out) {
     vecchia_clear_error();
-    if (!out) return vecchia_set_error(VECCHIA_EINVAL, "graph_build: out is NULL");
-    *out = nullptr;
-    if (!x) return vecchia_set_error(VECCHIA_EINVAL, "graph_build: x is NULL");
-    if (n < 1 || n >= (int64_t(1) << 31)) return vecchia_set_error(VECCHIA_EINVAL, "graph_build: need 1 <= N < 2^31, got %lld", (long long)n);
-    if (d < 1 || d > 3) return vecchia_set_error(VECCHIA_EINVAL, "graph_build: need 1 <= d <= 3, got %d", d);
-    if (k < 1) return vecchia_set_error(VECCHIA_EINVAL, "graph_build: need k >= 1, got %d", k);
-    if (k > VECCHIA_KMAX)
-        return vecchia_set_error(VECCHIA_EUNSUPPORTED, "graph_build: k=%d exceeds the compiled maximum %d", k, VECCHIA_KMAX);
-    if (n0 < 1 || n0 > n) return vecchia_set_error(VECCHIA_EINVAL, "graph_build: need 1 <= n0 <= N, got n0=%d", n0);
-    for (int64_t i = 0; i < n * d; ++i)
-        if (!std::isfinite(x[i])) return vecchia_set_error(VECCHIA_EINVAL, "graph_build: non-finite coordinate at point %lld", (long long)(i / d));
-    int nthreads = n_threads > 0 ? n_threads : (int)std::max(1u, std::thread::hardware_concurrency());
+    int rc = check_build_args(x, n, d, k, n0, out, "graph_build");
+    if (rc) return rc;
     vecchia_graph* g = nullptr;
     try {
-        g = new vecchia_graph();
-        g->n = n;
-        g->d = d;
-        g->k = k;
-        g->kp = vecchia_padded_k(k);
-        g->n0 = n0;
-        g->nthreads = nthreads;
+        g = begin_graph(x, n, d, k, n0, threads_of(n_threads));
         auto t0 = std::chrono::steady_clock::now();
-        build_tree(*g, x, nthreads);
-        g->times[0] = seconds_since(t0);
-        t0 = std::chrono::steady_clock::now();
-        build_neighbours(*g, nthreads);
+        build_neighbours(*g, g->nthreads);
         g->times[1] = seconds_since(t0);
-        t0 = std::chrono::steady_clock::now();
-        build_depth(*g, nthreads);
-        g->times[2] = seconds_since(t0);
-        t0 = std::chrono::steady_clock::now();
-        build_storage(*g);
-        g->times[3] = seconds_since(t0);
+        finish_graph(*g);
     } catch (const std::bad_alloc&) {
         delete g;
         return vecchia_set_error(VECCHIA_ENOMEM, "graph_build: host allocation failed (N=%lld, k=%d)", (long long)n, k);
     }
     *out = g;
+    return VECCHIA_OK;
+}
+
+extern "C" int graph_build_begin(const double* x, int64_t n, int32_t d, int32_t k, int32_t n0, int32_t n_threads,
+                                 vecchia_graph** out) {
+    vecchia_clear_error();
+    int rc = check_build_args(x, n, d, k, n0, out, "graph_build_begin");
+    if (rc) return rc;
+    vecchia_graph* g = nullptr;
+    try {
+        g = begin_graph(x, n, d, k, n0, threads_of(n_threads));
+        g->pending = true;
+    } catch (const std::bad_alloc&) {
+        delete g;
+        return vecchia_set_error(VECCHIA_ENOMEM, "graph_build_begin: host allocation failed (N=%lld)", (long long)n);
+    }
+    *out = g;
+    return VECCHIA_OK;
+}
+
+extern "C" int graph_knn_nodes(const vecchia_graph* g, void* nodes, int32_t* rank_of) {
+    if (!g || !nodes || !rank_of) return vecchia_set_error(VECCHIA_EINVAL, "graph_knn_nodes: NULL argument");
+    KnnNode* out = static_cast<KnnNode*>(nodes);
+    const int64_t n = g->n;
+    parallel_for(n, 1 << 16, g->nthreads, [&](int64_t a, int64_t b) {
+        for (int64_t r = a; r < b; ++r) {
+            const int64_t t = g->seq[r];
+            KnnNode& nd = out[r];
+            for (int c = 0; c < 3; ++c) nd.c[c] = g->xs[t * 3 + c];
+            nd.slot = (int32_t)t;
+            const int64_t l = left_child(t), rr = right_child(t);
+            nd.left = l < n ? g->rank_of[l] : -1;
+            nd.right = rr < n ? g->rank_of[rr] : -1;
+            nd.sdim = g->sdim[t];
+        }
+    });
+    std::memcpy(rank_of, g->rank_of.data(), (size_t)n * sizeof(int32_t));
+    return VECCHIA_OK;
+}
+
+extern "C" int graph_build_finish(vecchia_graph* g, const int32_t* rows) {
+    vecchia_clear_error();
+    if (!g || !rows) return vecchia_set_error(VECCHIA_EINVAL, "graph_build_finish: NULL argument");
+    if (!g->pending) return vecchia_set_error(VECCHIA_EINVAL, "graph_build_finish: graph is not pending");
+    const int64_t ns = g->n - g->n0;
+    const int k = g->k;
+    // rows come from outside the builder: every entry must name a preceding
+    // slot, rows ascend by key, and padding (-1) only fills the tail of the
+    // rows of slots with fewer than k predecessors
+    std::atomic<int64_t> first_bad(ns);      // smallest failing row, ns if none
+    parallel_for(ns, 1 << 14, g->nthreads, [&](int64_t a, int64_t b) {
+        for (int64_t r = a; r < b; ++r) {
+            const int64_t i = g->n0 + r;
+            const int64_t want = std::min<int64_t>(k, i);
+            const double* q = &g->xs[i * 3];
+            double prev_d = -1.0;
+            int32_t prev_j = -1;
+            bool ok = true;
+            for (int m = 0; m < k && ok; ++m) {
+                const int32_t j = rows[r * k + m];
+                if (m < want ? (j < 0 || j >= i) : (j != -1)) ok = false;
+                if (!ok || j < 0) continue;
+                const double dd = sqdist(q, &g->xs[(int64_t)j * 3], g->d);
+                if (m > 0 && !(dd > prev_d || (dd == prev_d && j > prev_j))) ok = false;
+                prev_d = dd;
+                prev_j = j;
+            }
+            if (!ok) {
+                int64_t cur = first_bad.load();
+                while (r < cur && !first_bad.compare_exchange_weak(cur, r)) {
+                }
+            }
+        }
+    });
+    if (first_bad.load() < ns)
+        return vecchia_set_error(VECCHIA_EINVAL,
+                                 "graph_build_finish: the row of slot %lld names a slot that does not precede it, is "
+                                 "padded before its end, or is not ascending by (distance, slot)",
+                                 (long long)(g->n0 + first_bad.load()));
+    try {
+        g->nbr.resize((size_t)ns * k);
+        parallel_for(ns, 1 << 14, g->nthreads, [&](int64_t a, int64_t b) {
+            for (int64_t q = a * k; q < b * k; ++q) g->nbr[q] = rows[q] >= 0 ? g->rank_of[rows[q]] : -1;
+        });
+        finish_graph(*g);
+    } catch (const std::bad_alloc&) {
+        return vecchia_set_error(VECCHIA_ENOMEM, "graph_build_finish: host allocation failed");
+    }
     return VECCHIA_OK;
 }
 
@@ -486,6 +602,7 @@ extern "C" int graph_info(const vecchia_graph* g, int64_t* n, int32_t* d, int32_
 
 extern "C" int graph_export(const vecchia_graph* g, int32_t* order, int32_t* slot, int32_t* level_ptr,
                             int32_t* depth) {
+    if (g && g->pending) return vecchia_set_error(VECCHIA_EINVAL, "graph_export: the graph is pending (graph_build_finish)");
     if (!g) return vecchia_set_error(VECCHIA_EINVAL, "graph_export: graph is NULL");
     for (int64_t s = 0; s < g->n; ++s) {
         const int32_t t = g->order[s];
@@ -498,6 +615,7 @@ extern "C" int graph_export(const vecchia_graph* g, int32_t* order, int32_t* slo
 }
 
 extern "C" int graph_export_nbr(const vecchia_graph* g, int32_t layout, int32_t* nbr) {
+    if (g && g->pending) return vecchia_set_error(VECCHIA_EINVAL, "graph_export_nbr: the graph is pending (graph_build_finish)");
     if (!g || !nbr) return vecchia_set_error(VECCHIA_EINVAL, "graph_export_nbr: NULL argument");
     if (layout != 0 && layout != 1) return vecchia_set_error(VECCHIA_EINVAL, "graph_export_nbr: layout must be 0 or 1");
     const int64_t ns = g->n - g->n0;
@@ -540,6 +658,7 @@ extern "C" int graph_export_points(const vecchia_graph* g, int32_t precision, vo
 }
 
 extern "C" int graph_export_children(const vecchia_graph* g, int64_t* child_ptr, int32_t* child) {
+    if (g && g->pending) return vecchia_set_error(VECCHIA_EINVAL, "graph_export_children: the graph is pending (graph_build_finish)");
     if (!g || !child_ptr || !child) return vecchia_set_error(VECCHIA_EINVAL, "graph_export_children: NULL argument");
     const int64_t ns = g->n - g->n0;
     if (ns * g->kp >= (int64_t(1) << 31))

@@ -45,7 +45,10 @@ class Graph:
     """Bit-reversed k-d tree order, preceding k-NN and depth batches of a
     point cloud, built on the host by the native library."""
 
-    def __init__(self, x, k, n0, n_threads=0):
+    def __init__(self, x, k, n0, n_threads=0, knn_device=None):
+        """knn_device (e.g. "cuda:0"): run the preceding k-NN search on that
+        device (graph_build_begin / graph_knn_device / graph_build_finish);
+        the result is the same graph bit for bit."""
         x = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
         if x.ndim == 1:
             x = x[:, None]
@@ -53,9 +56,33 @@ class Graph:
             raise ValueError("points must be (N, d)")
         self._lib = _lib.load()
         handle = ctypes.c_void_p()
-        _lib.check(self._lib.graph_build(x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), x.shape[0], x.shape[1],
-                                         int(k), int(n0), int(n_threads), ctypes.byref(handle)), "graph_build")
-        self._h = handle
+        xp = x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        self.knn_seconds = None
+        if knn_device is None:
+            _lib.check(self._lib.graph_build(xp, x.shape[0], x.shape[1], int(k), int(n0), int(n_threads),
+                                             ctypes.byref(handle)), "graph_build")
+            self._h = handle
+        else:
+            import time
+            _lib.check(self._lib.graph_build_begin(xp, x.shape[0], x.shape[1], int(k), int(n0), int(n_threads),
+                                                   ctypes.byref(handle)), "graph_build_begin")
+            self._h = handle
+            n = x.shape[0]
+            nodes = np.empty(n * _lib.KNN_NODE_BYTES, np.uint8)
+            rank_of = np.empty(n, np.int32)
+            _lib.check(self._lib.graph_knn_nodes(self._h, _ptr(nodes), _ptr(rank_of)), "graph_knn_nodes")
+            dev = torch.device(knn_device)
+            t0 = time.perf_counter()
+            nodes_d = torch.from_numpy(nodes).to(dev)
+            rank_d = torch.from_numpy(rank_of).to(dev)
+            rows_d = torch.empty(max((n - int(n0)) * int(k), 1), dtype=torch.int32, device=dev)
+            _lib.check(self._lib.graph_knn_device(ctypes.c_void_p(nodes_d.data_ptr()), ctypes.c_void_p(rank_d.data_ptr()),
+                                                  n, x.shape[1], int(k), int(n0), ctypes.c_void_p(rows_d.data_ptr()),
+                                                  _stream(dev)), "graph_knn_device")
+            rows = rows_d.cpu().numpy()
+            self.knn_seconds = time.perf_counter() - t0
+            del nodes_d, rank_d, rows_d
+            _lib.check(self._lib.graph_build_finish(self._h, _ptr(rows)), "graph_build_finish")
         n, d, kk, kp, nn0, nl = (ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(),
                                  ctypes.c_int32(), ctypes.c_int32())
         _lib.check(self._lib.graph_info(self._h, ctypes.byref(n), ctypes.byref(d), ctypes.byref(kk),

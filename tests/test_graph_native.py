@@ -168,3 +168,56 @@ def test_row_order_helper_inverts_the_device_order():
         assert (back[~pad] == rm[~pad]).all() and (back[pad] == -1).all()
         rows = np.array([0, 7, g.ns - 1])
         assert (g.to_row_order(dev[rows].astype(np.int64), rows)[~pad[rows]] == rm[rows][~pad[rows]]).all()
+
+
+def _begin(x, k, n0):
+    lib = _lib.load()
+    import ctypes
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    h = ctypes.c_void_p()
+    _lib.check(lib.graph_build_begin(x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), x.shape[0], x.shape[1], k,
+                                     n0, 2, ctypes.byref(h)), "graph_build_begin")
+    return lib, h
+
+
+@pytest.mark.parametrize("n,d,k,n0,seed", [(1500, 3, 8, 32, 40), (900, 2, 16, 4, 41), (300, 3, 64, 1, 42)])
+def test_split_build_with_brute_force_rows_equals_graph_build(n, d, k, n0, seed):
+    """graph_build_begin + graph_build_finish fed the oracle's brute-force
+    rows (tree slots, ascending (D, slot), -1 padded) gives exactly the graph
+    of graph_build: the order, the batches and every exported row."""
+    import ctypes
+    x = np.random.default_rng(seed).random((n, d))
+    og = oracle.build_graph(x, k, n0)
+    lib, h = _begin(x, k, n0)
+    rows = np.ascontiguousarray(og.nbr.astype(np.int32))
+    assert lib.graph_export_nbr(h, 0, ctypes.c_void_p(np.empty(1, np.int32).ctypes.data)) == _lib.EINVAL  # pending
+    _lib.check(lib.graph_build_finish(h, ctypes.c_void_p(rows.ctypes.data)), "graph_build_finish")
+    ref = Graph(x, k, n0)
+    got_order = np.empty(n, np.int32)
+    got_lp = np.empty(ref.n_levels + 2, np.int32)
+    _lib.check(lib.graph_export(h, ctypes.c_void_p(got_order.ctypes.data), None, ctypes.c_void_p(got_lp.ctypes.data),
+                                None), "graph_export")
+    assert (got_order == ref.order).all() and (got_lp == ref.level_ptr).all()
+    for layout in (0, 1):
+        size = (n - n0) * k if layout == 0 else ref.ntiles * ref.kp * 64
+        got = np.empty(max(size, 1), np.int32)
+        _lib.check(lib.graph_export_nbr(h, layout, ctypes.c_void_p(got.ctypes.data)), "graph_export_nbr")
+        assert (got[:size] == ref.nbr(layout).reshape(-1)).all()
+    lib.graph_free(h)
+
+
+def test_split_build_rejects_bad_rows():
+    import ctypes
+    x = np.random.default_rng(5).random((400, 3))
+    og = oracle.build_graph(x, 8, 16)
+    for mutate in ("later_slot", "order", "missing"):
+        rows = np.ascontiguousarray(og.nbr.astype(np.int32))
+        if mutate == "later_slot":
+            rows[100, 0] = 16 + 100           # its own slot: not a predecessor
+        elif mutate == "order":
+            rows[200, [0, 1]] = rows[200, [1, 0]]
+        else:
+            rows[300, 3] = -1                 # padding inside a full row
+        lib, h = _begin(x, 8, 16)
+        assert lib.graph_build_finish(h, ctypes.c_void_p(rows.ctypes.data)) == _lib.EINVAL, mutate
+        lib.graph_free(h)
