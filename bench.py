@@ -165,6 +165,8 @@ def main():
                     help="skip the comparisons (FP64 path on the same workload, k=16 radial in both precisions)")
     ap.add_argument("--serve-requests", type=int, default=128,
                     help="requests of the serving measurement (0 skips it)")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="run only the gradient configuration (2^22 radial, k = 16) and print its record")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -174,6 +176,10 @@ def main():
 
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.adjoint_only:
+        import torch
+        print(json.dumps({"adjoint_radial_2e22": adjoint_step(args.steps, torch.device("cuda:0"))}), flush=True)
         return
 
     import workloads
@@ -207,6 +213,7 @@ def main():
     graph_phases = {a: round(b, 2) for a, b in g.build_times().items()}
     if g.knn_seconds is not None:
         graph_phases["neighbours"] = round(g.knn_seconds, 2)      # device search incl. transfers
+        graph_phases["split"] = {a: round(b, 2) for a, b in g.split_seconds.items()}
     log("graph: %.1fs %s, %d levels (neighbour search on the %s)" % (graph_s, graph_phases, g.n_levels,
                                                                       "host" if args.host_knn else "device"))
     t = time.time()
@@ -464,10 +471,34 @@ def same_distribution_k16(w, n, steps, dev, threads):
     return res
 
 
+def sweep_bytes(n, ns, k, esz):
+    """Algorithmic bytes of the reverse sweep (w = (I - B)^-T vbar by batches,
+    a gather over the children lists): per edge the packed child entry (4),
+    its coefficient (esz) and the child's w (8, double); per point its two
+    children offsets (8, each read once), vbar (esz), w written (8); per
+    sparse point sigma (esz) and xibar written (esz)."""
+    return ns * k * (12 + esz) + n * (16 + esz) + ns * 2 * esz
+
+
+def theta_laneops_per_point(k, kind):
+    """Algorithmic VALU lane-operations of the theta kernel for one sparse
+    point: K_cc and its Cholesky again (the factor's count without the
+    coefficient solve), the two solves of u = K_cc^-1 bbar (k^2), and the
+    derivatives of the k(k+1)/2 distinct entries of K_cc and of the k
+    entries of k_ci, each a kernel evaluation with its ell-derivative (about
+    six operations more than the value alone) and two accumulations."""
+    per_eval = {0: 12, 1: 16, 2: 11, 3: 18}[kind]
+    factor = k * (k + 1) // 2 * per_eval + k ** 3 / 6.0 + k * k / 2.0 + 8 * k
+    return factor + k * k + (k * (k + 1) // 2 + k) * (per_eval + 6 + 2)
+
+
 def adjoint_step(steps, dev):
     """The gradient configuration (2^22 radial points, Matern-3/2, k = 16,
     FP32 path): factor + forward + logdet, then the reverse sweep and the
-    theta kernel for loss = 1/2 |v - y|^2 / s^2 + logdet, s = 0.1."""
+    theta kernel for loss = 1/2 |v - y|^2 / s^2 + logdet, s = 0.1.  The
+    parts are timed with events on the library's stream: the backward with
+    logdet_bar only runs the theta kernel (and the dense block) without the
+    sweep, so the sweep's time is the difference of the two backward calls."""
     import torch
     import workloads
     from paper_2606_11402_amd import FP32, Factor, Graph, KernelParams
@@ -495,8 +526,42 @@ def adjoint_step(steps, dev):
         theta = step()
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
+
+    def timed(fn, reps):
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(reps):
+            fn()
+        ev1.record()
+        ev1.synchronize()
+        return ev0.elapsed_time(ev1) / reps
+
+    vbar = (v - y) / 0.01
+    reps = max(steps, 3)
+    t_factor = timed(fac.refactor, reps)
+    t_forward = timed(lambda: fac.forward(xi, out=v), reps)
+    t_full = timed(lambda: fac.backward(xi, v, v_bar=vbar, logdet_bar=1.0, scratch=scratch), reps)
+    t_theta = timed(lambda: fac.backward(xi, v, logdet_bar=1.0, scratch=scratch), reps)
+    t_sweep = max(t_full - t_theta, 1e-6)
+    ns = w.n - w.n0
+    sb = sweep_bytes(w.n, ns, w.k, 4)
+    tl = theta_laneops_per_point(w.k, w.kind) * ns
     res = {"n": w.n, "k": w.k, "ms_per_step": round(ms, 3), "points_per_s": w.n / (ms * 1e-3),
-           "step": "factor + forward + reverse sweep + theta kernel", "theta_bar": [float(t) for t in theta.cpu()]}
+           "step": "factor + forward + reverse sweep + theta kernel", "theta_bar": [float(t) for t in theta.cpu()],
+           "parts_ms": {"factor": round(t_factor, 3), "forward": round(t_forward, 3),
+                        "backward": round(t_full, 3), "theta_and_dense": round(t_theta, 3),
+                        "sweep": round(t_sweep, 3)},
+           "levels": g.n_levels,
+           "rooflines": {
+               "sweep": {"bound": "hbm", "achieved": round(sb / (t_sweep * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(sb / (t_sweep * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                         "per_unit": "%.0f B per sparse point (k edges of 16 B, the point's own 28 B)" % (sb / ns),
+                         "launches": g.n_levels + 1},
+               "theta": {"bound": "alu", "achieved": round(tl / (t_theta * 1e-3) / 1e12, 3),
+                         "peak": VALU_PEAK_TLANEOPS, "unit": "T lane-op/s",
+                         "frac": round(tl / (t_theta * 1e-3) / 1e12 / VALU_PEAK_TLANEOPS, 4),
+                         "per_unit": "%.0f lane-ops per sparse point" % (tl / ns),
+                         "note": "time of the backward with logdet_bar only: theta kernel + dense block + reduction"}}}
     log("adjoint:", res)
     return res
 

@@ -23,21 +23,48 @@
 
 namespace vk {
 
-// ---- reverse sweep of one batch: w_j = vbar_j + sum_children b w_child
-template <typename TS, int KP>
+// ---- reverse sweep of one batch: w_j = vbar_j + sum_children b w_child.
+// A group of G lanes serves one node: lane t takes the children t, t + G, ...
+// and the group sums its parts in a fixed butterfly, so the result does not
+// depend on timing.  Child counts fall from a few hundred in the first, small
+// batches to a few in the last, large ones; the host picks G per batch from
+// its size so that the longest list of a batch takes a few rounds of
+// gathers instead of hundreds.
+template <typename TS, int KP, int G>
 __global__ __launch_bounds__(kBlock) void adj_sweep_kernel(AdjArgs<TS> a, int64_t j_begin, int64_t j_end) {
+    static_assert(kBlock % G == 0, "a group never straddles workgroups");
     constexpr int SH = KP == 8 ? 3 : (KP == 16 ? 4 : (KP == 32 ? 5 : 6));
-    const int64_t j = j_begin + (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (j >= j_end) return;
-    double acc = (double)a.vbar[j];
-    for (int64_t e = a.child_ptr[j]; e < a.child_ptr[j + 1]; ++e) {
+    const int64_t j = j_begin + ((int64_t)blockIdx.x * kBlock + threadIdx.x) / G;
+    const int t = threadIdx.x % G;
+    const bool live = j < j_end;                   // the same for the whole group
+    const int64_t jj = live ? j : j_end - 1;       // dead groups mirror a live node and write nothing
+    const int64_t e1 = a.child_ptr[jj + 1];
+    double acc = 0.0;
+    for (int64_t e = a.child_ptr[jj] + t; e < e1; e += G) {
         const int32_t packed = a.child[e];
         const int64_t sp = packed >> SH;
         const int m = packed & (KP - 1);
         acc = fma((double)a.b[((sp >> 6) * KP + m) * kTile + (sp & 63)], a.w[a.n0 + sp], acc);
     }
-    a.w[j] = acc;
-    if (j >= a.n0) a.xibar[j] = (TS)((double)a.sigma[j - a.n0] * acc);
+    acc = group_sum<G>(acc) + (double)a.vbar[jj];
+    if (live && t == 0) {
+        a.w[j] = acc;
+        if (j >= a.n0) a.xibar[j] = (TS)((double)a.sigma[j - a.n0] * acc);
+    }
+}
+
+template <typename TS, int KP>
+static hipError_t launch_adj_sweep(const AdjArgs<TS>& a, int64_t j0, int64_t j1, hipStream_t s) {
+    const int64_t nodes = j1 - j0;
+    auto go = [&](auto GI) {
+        constexpr int G = decltype(GI)::value;
+        hipLaunchKernelGGL((adj_sweep_kernel<TS, KP, G>), dim3((unsigned)((nodes * G + kBlock - 1) / kBlock)),
+                           dim3(kBlock), 0, s, a, j0, j1);
+        return hipGetLastError();
+    };
+    if (nodes <= 4096) return go(std::integral_constant<int, 64>{});
+    if (nodes <= 65536) return go(std::integral_constant<int, 16>{});
+    return go(std::integral_constant<int, 4>{});
 }
 
 // ---- inverse part: vbar_j = z_j - sum_children b z_child, z = xibar / sigma
@@ -136,6 +163,16 @@ __global__ __launch_bounds__(kBlock) void adj_theta_kernel(AdjArgs<TS> a) {
         acc_s = fma(coef, 2.0 * kap * inv_amp, acc_s);
         acc_l = fma(coef, dl, acc_l);
     });
+    // sum_{i,j} cw_i b_j dK_ij with cw_i = sbar b_i - u_i over the distinct
+    // entries of the symmetric dK: the diagonal with weight cw_i b_i, each
+    // entry below it with cw_i b_j + cw_j b_i.  For column q the lane takes
+    // its row blocks from q's block down; rows of that block above the
+    // diagonal get weight 0.
+    double cw[R];
+    static_for<0, R>([&](auto PI) {
+        constexpr int p = PI;
+        cw[p] = sbar * bq[p] - u[p];
+    });
     static_for<0, K>([&](auto QI) {
         constexpr int q = QI, pq = q / P, rq = q % P;
         const double y0 = group_bcast<P, rq>(c0[pq]);
@@ -143,17 +180,20 @@ __global__ __launch_bounds__(kBlock) void adj_theta_kernel(AdjArgs<TS> a) {
         const double y2 = group_bcast<P, rq>(c2[pq]);
         const int okq = group_bcast<P, rq>(ok[pq]);
         const double bqq = group_bcast<P, rq>(bq[pq]);
-        static_for<0, R>([&](auto PI) {
+        const double cwq = group_bcast<P, rq>(cw[pq]);
+        static_for<pq, R>([&](auto PI) {
             constexpr int p = PI;
             double kap, dl;
             cov_and_dell<KIND>(sqdist3(c0[p], c1[p], c2[p], y0, y1, y2), a.cov, kap, dl);
             const bool both = (ok[p] & okq) != 0;
-            const bool same = (p * P + r) == q;
+            const int row = p * P + r;
+            const bool same = row == q;
             const double ds = both ? (same ? 2.0 * a.sigma_amp : 2.0 * kap * inv_amp) : 0.0;
             const double dll = (both && !same) ? dl : 0.0;
-            const double ap = (sbar * bq[p] - u[p]) * bqq;
-            acc_s = fma(ap, ds, acc_s);
-            acc_l = fma(ap, dll, acc_l);
+            double wgt = same ? cw[p] * bqq : fma(cw[p], bqq, cwq * bq[p]);
+            if constexpr (p == pq) wgt = row < q ? 0.0 : wgt;
+            acc_s = fma(wgt, ds, acc_s);
+            acc_l = fma(wgt, dll, acc_l);
         });
     });
     acc_s = group_sum<P>(acc_s);
@@ -302,9 +342,7 @@ static hipError_t backward_t(const BackwardLaunch& p, hipStream_t s) {
         for (int l = p.n_levels; l >= 0; --l) {
             const int64_t j0 = l == 0 ? 0 : p.level_ptr[l], j1 = l == 0 ? p.n0 : p.level_ptr[l + 1];
             if (j1 <= j0) continue;
-            hipLaunchKernelGGL((adj_sweep_kernel<TS, KP>), dim3((unsigned)((j1 - j0 + kBlock - 1) / kBlock)),
-                               dim3(kBlock), 0, s, a, j0, j1);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
+            if ((e = launch_adj_sweep<TS, KP>(a, j0, j1, s)) != hipSuccess) return e;
         }
     }
     if (p.xibar_in) {

@@ -50,13 +50,16 @@ __device__ __forceinline__ int group_bcast_i32(int v) {
     }
 }
 
-// 32-bit value of the lane whose index differs by X (X in {1, 2, 4, 8, 16}).
+// 32-bit value of the lane whose index differs by X (X in {1, 2, 4, 8, 16,
+// 32}; 32 crosses the halves of the wave, through ds_bpermute).
 template <int X>
 __device__ __forceinline__ int group_xor_i32(int v) {
     if constexpr (X == 1) {
         return __builtin_amdgcn_mov_dpp(v, 1 | (0 << 2) | (3 << 4) | (2 << 6), 0xF, 0xF, true);
     } else if constexpr (X == 2) {
         return __builtin_amdgcn_mov_dpp(v, 2 | (3 << 2) | (0 << 4) | (1 << 6), 0xF, 0xF, true);
+    } else if constexpr (X == 32) {
+        return __shfl_xor(v, 32, 64);
     } else {
         static_assert(X == 4 || X == 8 || X == 16, "xor distance");
         return __builtin_amdgcn_ds_swizzle(v, 0x1F | (X << 10));
@@ -103,6 +106,7 @@ __device__ __forceinline__ T group_sum(T v) {
     if constexpr (P >= 8) v = v + group_xor<4>(v);
     if constexpr (P >= 16) v = v + group_xor<8>(v);
     if constexpr (P >= 32) v = v + group_xor<16>(v);
+    if constexpr (P >= 64) v = v + group_xor<32>(v);
     return v;
 }
 

@@ -58,12 +58,14 @@ class Graph:
         handle = ctypes.c_void_p()
         xp = x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         self.knn_seconds = None
+        self.split_seconds = None       # device path: wall time of each host and device step
         if knn_device is None:
             _lib.check(self._lib.graph_build(xp, x.shape[0], x.shape[1], int(k), int(n0), int(n_threads),
                                              ctypes.byref(handle)), "graph_build")
             self._h = handle
         else:
             import time
+            ts = [time.perf_counter()]
             _lib.check(self._lib.graph_build_begin(xp, x.shape[0], x.shape[1], int(k), int(n0), int(n_threads),
                                                    ctypes.byref(handle)), "graph_build_begin")
             self._h = handle
@@ -72,7 +74,7 @@ class Graph:
             rank_of = np.empty(n, np.int32)
             _lib.check(self._lib.graph_knn_nodes(self._h, _ptr(nodes), _ptr(rank_of)), "graph_knn_nodes")
             dev = torch.device(knn_device)
-            t0 = time.perf_counter()
+            ts.append(time.perf_counter())
             nodes_d = torch.from_numpy(nodes).to(dev)
             rank_d = torch.from_numpy(rank_of).to(dev)
             rows_d = torch.empty(max((n - int(n0)) * int(k), 1), dtype=torch.int32, device=dev)
@@ -80,9 +82,13 @@ class Graph:
                                                   n, x.shape[1], int(k), int(n0), ctypes.c_void_p(rows_d.data_ptr()),
                                                   _stream(dev)), "graph_knn_device")
             rows = rows_d.cpu().numpy()
-            self.knn_seconds = time.perf_counter() - t0
+            ts.append(time.perf_counter())
+            self.knn_seconds = ts[-1] - ts[-2]
             del nodes_d, rank_d, rows_d
             _lib.check(self._lib.graph_build_finish(self._h, _ptr(rows)), "graph_build_finish")
+            ts.append(time.perf_counter())
+            self.split_seconds = {"begin_and_nodes": ts[1] - ts[0], "device_search": ts[2] - ts[1],
+                                  "finish": ts[3] - ts[2]}
         n, d, kk, kp, nn0, nl = (ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(),
                                  ctypes.c_int32(), ctypes.c_int32())
         _lib.check(self._lib.graph_info(self._h, ctypes.byref(n), ctypes.byref(d), ctypes.byref(kk),
