@@ -446,7 +446,7 @@ def same_distribution_k16(w, n, steps, dev, threads):
     import torch
     from paper_2606_11402_amd import FP32, Factor, Graph, KernelParams
     from paper_2606_11402_amd import vecchia as vmod
-    g = Graph(w.points(n), 16, w.n0, n_threads=threads)
+    g = Graph(w.points(n), 16, w.n0, n_threads=threads, knn_device=str(dev))
     dg = g.to_device(FP32, dev)
     xi = torch.from_numpy(g.to_storage(w.xi(n))).float().to(dev)
     v = torch.empty(n, dtype=torch.float32, device=dev)
