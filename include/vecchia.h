@@ -120,6 +120,57 @@ int graph_knn_device(const void* nodes, const int32_t* rank_of, int64_t n, int32
                      int32_t* rows, void* stream);
 int graph_build_finish(vecchia_graph* g, const int32_t* rows);
 
+/* The depths of Sec. 2.2 on the device, as the parallel fixpoint of their
+ * recurrence (Sec. 2.3, last paragraph): the dense block (slots < n0) at 0,
+ * every sparse slot i at d_i = 1 + max d_j over its row.  rows (device): as
+ * graph_knn_device writes them; depth (device, N int32, tree slot order)
+ * receives the depths; scratch (device) holds one int32.  Each sparse slot
+ * starts at 1 and the sweeps raise it in place until a sweep changes nothing;
+ * the fixpoint is unique, so the result does not depend on the order of the
+ * updates.  Neighbours precede their point, so the slots are swept in
+ * consecutive blocks, in order, each until it is stable (the blocks before it
+ * are final).  The call synchronises `stream` every second sweep to test for
+ * a change and returns when the depths are final; *sweeps (may be NULL)
+ * receives the number of sweeps.  Errors: EINVAL, EHIP. */
+int graph_depth_device(const int32_t* rows, int64_t n, int32_t k, int32_t n0, int32_t* depth, int32_t* scratch,
+                       void* stream, int32_t* sweeps);
+
+/* graph_build_finish with the depths given (host, N int32, tree slot order,
+ * from graph_depth_device) instead of computed: they are checked against the
+ * recurrence (EINVAL naming the first slot that breaks it), then the batches
+ * and the storage order follow from them as in graph_build. */
+int graph_build_finish_depth(vecchia_graph* g, const int32_t* rows, const int32_t* depth);
+
+/* The bit-reversed left-balanced k-d tree of Sec. 2.2 on the device, by sort
+ * passes (Sec. 2.3, last paragraph), one tree level at a time: per level a
+ * stable radix sort of the points by their coordinate in their node's split
+ * dimension, then by node, makes every node's set a run ordered by
+ * (coordinate, input index); its point is the run's middle (rank |S|/2) and
+ * the parts below and above are its children's sets.  The split dimension of
+ * a node is the widest extent of its set (the lowest on ties).  The result is
+ * the tree graph_build makes, bit for bit.
+ *   x          (device) N x 3 doubles in input order, zero padded for d < 3;
+ *   tree_perm  (device, N int32) receives slot -> input index;
+ *   sdim       (device, N int32) receives each slot's split dimension;
+ *   scratch    (device, 256-byte aligned) graph_tree_scratch_bytes(N) bytes
+ *              (about 64 N bytes: keys, indices, per-node sizes and bounds,
+ *              sort temporaries).
+ * Enqueued on `stream`; the caller synchronises.  Errors: EINVAL, ENOMEM
+ * (scratch too small), EHIP. */
+int graph_tree_scratch_bytes(int64_t n, size_t* bytes);
+int graph_tree_device(const double* x, int64_t n, int32_t d, int32_t* tree_perm, int32_t* sdim, void* scratch,
+                      size_t scratch_bytes, void* stream);
+
+/* graph_build_begin with the tree given (host arrays from graph_tree_device)
+ * instead of built: the tree is checked against the points without being
+ * rebuilt -- tree_perm a permutation, every split dimension the widest extent
+ * of its subtree, every point of a left (right) subtree below (above) its
+ * node's point by (coordinate, input index) -- and EINVAL names the first
+ * slot that breaks it.  Otherwise as graph_build_begin (the graph is pending
+ * until graph_build_finish / graph_build_finish_depth). */
+int graph_build_begin_tree(const double* x, int64_t n, int32_t d, int32_t k, int32_t n0, int32_t n_threads,
+                           const int32_t* tree_perm, const int32_t* sdim, vecchia_graph** out);
+
 /* Sizes of a built graph (any pointer may be NULL).  kp = padded width of the
  * tiled layout; n_levels = number of sparse batches L. */
 int graph_info(const vecchia_graph* g, int64_t* n, int32_t* d, int32_t* k, int32_t* kp,

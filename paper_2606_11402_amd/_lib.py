@@ -59,6 +59,12 @@ _SIGNATURES = {
     "graph_knn_nodes": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "graph_knn_device": (c_int32, [c_void_p, c_void_p, c_int64, c_int32, c_int32, c_int32, c_void_p, c_void_p]),
     "graph_build_finish": (c_int32, [c_void_p, c_void_p]),
+    "graph_depth_device": (c_int32, [c_void_p, c_int64, c_int32, c_int32, c_void_p, c_void_p, c_void_p, P(c_int32)]),
+    "graph_build_finish_depth": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "graph_tree_scratch_bytes": (c_int32, [c_int64, P(c_size_t)]),
+    "graph_tree_device": (c_int32, [c_void_p, c_int64, c_int32, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "graph_build_begin_tree": (c_int32, [P(c_double), c_int64, c_int32, c_int32, c_int32, c_int32, c_void_p, c_void_p,
+                                         P(c_void_p)]),
     "graph_info": (c_int32, [c_void_p, P(c_int64), P(c_int32), P(c_int32), P(c_int32), P(c_int32), P(c_int32)]),
     "graph_export": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "graph_export_nbr": (c_int32, [c_void_p, c_int32, c_void_p]),

@@ -464,9 +464,87 @@ vecchia_graph* begin_graph(const double* x, int64_t n, int32_t d, int32_t k, int
     return g;
 }
 
-void finish_graph(vecchia_graph& g) {
+double canon_zero(double v) { return v == 0.0 ? 0.0 : v; }
+
+// Whether (perm, sdim) is the tree build_tree makes from x, checked without
+// rebuilding it (Sec. 2.2): perm is a permutation; the split dimension of
+// every slot is the widest extent of its subtree's points (the lowest on
+// ties); every point of a slot's left subtree is below, every point of its
+// right subtree above the slot's point by (coordinate in the split
+// dimension, input index).  The subtree sizes are fixed by N (left-balanced
+// slots), so these properties determine the tree.  One bottom-up pass
+// (deepest level first) keeps, per subtree and dimension, the smallest and
+// the largest (coordinate, index) key; a slot then compares its own key with
+// the largest of its left subtree and the smallest of its right one.
+// Returns the first failing slot, or -1.
+int64_t check_tree(const double* x, int64_t n, int d, const int32_t* perm, const int32_t* sdim, int nthreads) {
+    std::vector<uint8_t> seen(n, 0);
+    for (int64_t t = 0; t < n; ++t) {
+        const int32_t i = perm[t];
+        if (i < 0 || i >= n || seen[i] || sdim[t] < 0 || sdim[t] >= d) return t;
+        seen[i] = 1;
+    }
+    std::atomic<int64_t> bad(n);
+    auto fail = [&](int64_t t) {
+        int64_t cur = bad.load();
+        while (t < cur && !bad.compare_exchange_weak(cur, t)) {
+        }
+    };
+    struct Key {
+        double c;
+        int32_t id;
+    };
+    auto less = [](const Key& a, const Key& b) { return a.c < b.c || (a.c == b.c && a.id < b.id); };
+    std::vector<Key> lo((size_t)n * 3), hi((size_t)n * 3);
+    const int levels = tree_level(n - 1) + 1;
+    for (int l = levels - 1; l >= 0; --l) {
+        const int64_t first = (int64_t(1) << l) - 1, last = std::min<int64_t>(n, (int64_t(2) << l) - 1);
+        parallel_for(last - first, 1 << 12, nthreads, [&](int64_t a, int64_t b) {
+            for (int64_t t = first + a; t < first + b; ++t) {
+                const int32_t id = perm[t];
+                const int s = sdim[t];
+                const Key own{canon_zero(x[(int64_t)id * d + s]), id};
+                const int64_t lc = left_child(t), rc = right_child(t);
+                if (lc < n && !less(hi[lc * 3 + s], own)) fail(t);
+                if (rc < n && !less(own, lo[rc * 3 + s])) fail(t);
+                for (int c = 0; c < d; ++c) {
+                    Key k{canon_zero(x[(int64_t)id * d + c]), id};
+                    Key mn = k, mx = k;
+                    for (int64_t ch : {lc, rc}) {
+                        if (ch >= n) continue;
+                        if (less(lo[ch * 3 + c], mn)) mn = lo[ch * 3 + c];
+                        if (less(mx, hi[ch * 3 + c])) mx = hi[ch * 3 + c];
+                    }
+                    lo[t * 3 + c] = mn;
+                    hi[t * 3 + c] = mx;
+                }
+                int best = 0;
+                double bext = hi[t * 3].c - lo[t * 3].c;
+                for (int c = 1; c < d; ++c) {
+                    const double e = hi[t * 3 + c].c - lo[t * 3 + c].c;
+                    if (e > bext) {
+                        bext = e;
+                        best = c;
+                    }
+                }
+                if (s != best) fail(t);
+            }
+        });
+        if (bad.load() < n) return bad.load();
+    }
+    return -1;
+}
+
+void finish_graph(vecchia_graph& g, const int32_t* depth = nullptr) {
     auto t0 = std::chrono::steady_clock::now();
-    build_depth(g, g.nthreads);
+    if (depth) {
+        g.depth.assign(depth, depth + g.n);
+        int32_t maxd = 0;
+        for (int64_t t = g.n0; t < g.n; ++t) maxd = std::max(maxd, g.depth[t]);
+        g.n_levels = g.n > g.n0 ? maxd : 0;
+    } else {
+        build_depth(g, g.nthreads);
+    }
     g.times[2] = seconds_since(t0);
     t0 = std::chrono::steady_clock::now();
     build_storage(g);
@@ -517,6 +595,49 @@ extern "C" int graph_build_begin(const double* x, int64_t n, int32_t d, int32_t 
     return VECCHIA_OK;
 }
 
+extern "C" int graph_build_begin_tree(const double* x, int64_t n, int32_t d, int32_t k, int32_t n0,
+                                      int32_t n_threads, const int32_t* tree_perm, const int32_t* sdim,
+                                      vecchia_graph** out) {
+    vecchia_clear_error();
+    int rc = check_build_args(x, n, d, k, n0, out, "graph_build_begin_tree");
+    if (rc) return rc;
+    if (!tree_perm || !sdim) return vecchia_set_error(VECCHIA_EINVAL, "graph_build_begin_tree: NULL tree");
+    vecchia_graph* g = nullptr;
+    try {
+        const int nthreads = threads_of(n_threads);
+        auto t0 = std::chrono::steady_clock::now();
+        const int64_t bad = check_tree(x, n, d, tree_perm, sdim, nthreads);
+        if (bad >= 0)
+            return vecchia_set_error(VECCHIA_EINVAL, "graph_build_begin_tree: slot %lld breaks the tree of the points "
+                                     "(permutation, split dimension or median order)", (long long)bad);
+        g = new vecchia_graph();
+        g->n = n;
+        g->d = d;
+        g->k = k;
+        g->kp = vecchia_padded_k(k);
+        g->n0 = n0;
+        g->nthreads = nthreads;
+        g->tree_perm.assign(tree_perm, tree_perm + n);
+        g->sdim.resize(n);
+        for (int64_t t = 0; t < n; ++t) g->sdim[t] = (int8_t)sdim[t];
+        g->xs.resize((size_t)n * 3);
+        parallel_for(n, 1 << 16, nthreads, [&](int64_t a, int64_t b) {
+            for (int64_t t = a; t < b; ++t) {
+                const int64_t i = g->tree_perm[t];
+                for (int c = 0; c < 3; ++c) g->xs[t * 3 + c] = c < d ? x[i * d + c] : 0.0;
+            }
+        });
+        inorder(*g);
+        g->times[0] = seconds_since(t0);
+        g->pending = true;
+    } catch (const std::bad_alloc&) {
+        delete g;
+        return vecchia_set_error(VECCHIA_ENOMEM, "graph_build_begin_tree: host allocation failed (N=%lld)", (long long)n);
+    }
+    *out = g;
+    return VECCHIA_OK;
+}
+
 extern "C" int graph_knn_nodes(const vecchia_graph* g, void* nodes, int32_t* rank_of) {
     if (!g || !nodes || !rank_of) return vecchia_set_error(VECCHIA_EINVAL, "graph_knn_nodes: NULL argument");
     KnnNode* out = static_cast<KnnNode*>(nodes);
@@ -537,7 +658,9 @@ extern "C" int graph_knn_nodes(const vecchia_graph* g, void* nodes, int32_t* ran
     return VECCHIA_OK;
 }
 
-extern "C" int graph_build_finish(vecchia_graph* g, const int32_t* rows) {
+namespace {
+
+int finish_with(vecchia_graph* g, const int32_t* rows, const int32_t* depth) {
     vecchia_clear_error();
     if (!g || !rows) return vecchia_set_error(VECCHIA_EINVAL, "graph_build_finish: NULL argument");
     if (!g->pending) return vecchia_set_error(VECCHIA_EINVAL, "graph_build_finish: graph is not pending");
@@ -581,11 +704,44 @@ extern "C" int graph_build_finish(vecchia_graph* g, const int32_t* rows) {
         parallel_for(ns, 1 << 14, g->nthreads, [&](int64_t a, int64_t b) {
             for (int64_t q = a * k; q < b * k; ++q) g->nbr[q] = rows[q] >= 0 ? g->rank_of[rows[q]] : -1;
         });
-        finish_graph(*g);
+        if (depth) {
+            // depths from outside the builder: the dense block at 0 and every
+            // sparse slot one above its deepest neighbour (Sec. 2.2)
+            std::atomic<int64_t> bad(g->n);
+            parallel_for(g->n, 1 << 14, g->nthreads, [&](int64_t a, int64_t b) {
+                for (int64_t i = a; i < b; ++i) {
+                    int32_t want = 0;
+                    if (i >= g->n0) {
+                        const int32_t* row = &rows[(i - g->n0) * k];
+                        int32_t m = 0;
+                        for (int q = 0; q < k && row[q] >= 0; ++q) m = std::max(m, depth[row[q]]);
+                        want = m + 1;
+                    }
+                    if (depth[i] != want) {
+                        int64_t cur = bad.load();
+                        while (i < cur && !bad.compare_exchange_weak(cur, i)) {
+                        }
+                    }
+                }
+            });
+            if (bad.load() < g->n)
+                return vecchia_set_error(VECCHIA_EINVAL, "graph_build_finish_depth: the depth of slot %lld does not "
+                                         "follow the recurrence", (long long)bad.load());
+        }
+        finish_graph(*g, depth);
     } catch (const std::bad_alloc&) {
         return vecchia_set_error(VECCHIA_ENOMEM, "graph_build_finish: host allocation failed");
     }
     return VECCHIA_OK;
+}
+
+}  // namespace
+
+extern "C" int graph_build_finish(vecchia_graph* g, const int32_t* rows) { return finish_with(g, rows, nullptr); }
+
+extern "C" int graph_build_finish_depth(vecchia_graph* g, const int32_t* rows, const int32_t* depth) {
+    if (!depth) return vecchia_set_error(VECCHIA_EINVAL, "graph_build_finish_depth: depth is NULL");
+    return finish_with(g, rows, depth);
 }
 
 extern "C" int graph_info(const vecchia_graph* g, int64_t* n, int32_t* d, int32_t* k, int32_t* kp, int32_t* n0,

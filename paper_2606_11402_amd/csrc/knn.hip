@@ -11,6 +11,8 @@
 // search makes the same decisions).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "knn.h"
 #include "lanes.h"
 #include "status.h"
@@ -141,5 +143,83 @@ extern "C" int graph_knn_device(const void* nodes, const int32_t* rank_of, int64
     }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return vecchia_set_error(VECCHIA_EHIP, "graph_knn_device: %s", hipGetErrorString(e));
+    return VECCHIA_OK;
+}
+
+// ---- depths (Sec. 2.2: d_i = 1 + max over the neighbours' depths, the
+// dense block at depth 0) as the parallel fixpoint of that recurrence: every
+// sparse slot starts at 1 and each sweep raises d_i to 1 + max d_j, in place.
+// Depths only grow and are bounded by the longest chain of the neighbour
+// graph, so the sweeps end; the fixpoint is the longest-path depth, which is
+// unique, so neither the order of the updates nor stale reads of a slot that
+// another thread is raising change the result, only the number of sweeps.
+// Sweeps over all slots at once advance a chain of neighbours by about one
+// link each (measured: ~490 sweeps at 2^26); since every neighbour precedes
+// its point, the slots are instead taken in consecutive blocks, in order:
+// the depths of earlier blocks are final when a block starts, so a block
+// needs only as many sweeps as the chains inside it are long, usually one
+// or two.
+namespace {
+
+__global__ __launch_bounds__(256) void depth_init_kernel(int32_t* __restrict__ depth, int64_t n, int n0) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) depth[i] = i < n0 ? 0 : 1;
+}
+
+__global__ __launch_bounds__(256) void depth_sweep_kernel(const int32_t* __restrict__ rows, int64_t lo, int64_t hi,
+                                                          int k, int n0, int32_t* depth,
+                                                          int32_t* __restrict__ changed) {
+    const int64_t i = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= hi) return;
+    const int32_t* row = rows + (i - n0) * (int64_t)k;
+    int32_t m = 0;
+    for (int q = 0; q < k; ++q) {
+        const int32_t j = row[q];
+        if (j < 0) break;                         // padding only at the end of a row
+        m = max(m, __atomic_load_n(depth + j, __ATOMIC_RELAXED));
+    }
+    if (m + 1 > depth[i]) {
+        __atomic_store_n(depth + i, m + 1, __ATOMIC_RELAXED);
+        *changed = 1;
+    }
+}
+
+__global__ void flag_zero_kernel(int32_t* __restrict__ flag) { *flag = 0; }
+
+}  // namespace
+
+extern "C" int graph_depth_device(const int32_t* rows, int64_t n, int32_t k, int32_t n0, int32_t* depth,
+                                  int32_t* scratch, void* stream, int32_t* sweeps) {
+    vecchia_clear_error();
+    if (!rows || !depth || !scratch) return vecchia_set_error(VECCHIA_EINVAL, "graph_depth_device: NULL argument");
+    if (n < 1 || n >= (int64_t(1) << 31) || n0 < 1 || n0 > n || k < 1)
+        return vecchia_set_error(VECCHIA_EINVAL, "graph_depth_device: need 1 <= n0 <= N < 2^31 and k >= 1");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(depth_init_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, depth, n, n0);
+    hipError_t e = hipGetLastError();
+    int32_t done_sweeps = 0;
+    // per block: sweeps until one changes nothing (at most one per slot of the
+    // block, the longest chain inside it); the test costs a synchronisation,
+    // so it follows every second sweep (an extra sweep after the fixpoint
+    // changes nothing)
+    constexpr int64_t kDepthBlock = int64_t(1) << 16;
+    constexpr int kSweepsPerTest = 2;
+    for (int64_t lo = n0; e == hipSuccess && lo < n; lo += kDepthBlock) {
+        const int64_t hi = std::min(n, lo + kDepthBlock);
+        for (int64_t round = 0; round * kSweepsPerTest <= hi - lo; ++round) {
+            hipLaunchKernelGGL(flag_zero_kernel, dim3(1), dim3(1), 0, s, scratch);
+            for (int t = 0; t < kSweepsPerTest; ++t)
+                hipLaunchKernelGGL(depth_sweep_kernel, dim3((unsigned)((hi - lo + 255) / 256)), dim3(256), 0, s, rows,
+                                   lo, hi, k, n0, depth, scratch);
+            done_sweeps += kSweepsPerTest;
+            int32_t changed = 1;
+            if ((e = hipGetLastError()) != hipSuccess) break;
+            if ((e = hipMemcpyAsync(&changed, scratch, sizeof(changed), hipMemcpyDeviceToHost, s)) != hipSuccess) break;
+            if ((e = hipStreamSynchronize(s)) != hipSuccess) break;
+            if (!changed) break;
+        }
+    }
+    if (e != hipSuccess) return vecchia_set_error(VECCHIA_EHIP, "graph_depth_device: %s", hipGetErrorString(e));
+    if (sweeps) *sweeps = done_sweeps;
     return VECCHIA_OK;
 }

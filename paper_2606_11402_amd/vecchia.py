@@ -45,10 +45,13 @@ class Graph:
     """Bit-reversed k-d tree order, preceding k-NN and depth batches of a
     point cloud, built on the host by the native library."""
 
-    def __init__(self, x, k, n0, n_threads=0, knn_device=None):
+    def __init__(self, x, k, n0, n_threads=0, knn_device=None, depth_device=True, tree_device=True):
         """knn_device (e.g. "cuda:0"): run the preceding k-NN search on that
-        device (graph_build_begin / graph_knn_device / graph_build_finish);
-        the result is the same graph bit for bit."""
+        device (graph_build_begin / graph_knn_device / graph_build_finish),
+        with depth_device also the depth fixpoint (graph_depth_device /
+        graph_build_finish_depth) and with tree_device also the k-d tree
+        (graph_tree_device / graph_build_begin_tree); the result is the same
+        graph bit for bit."""
         x = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
         if x.ndim == 1:
             x = x[:, None]
@@ -58,6 +61,8 @@ class Graph:
         handle = ctypes.c_void_p()
         xp = x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         self.knn_seconds = None
+        self.tree_seconds = None
+        self.depth_sweeps = None
         self.split_seconds = None       # device path: wall time of each host and device step
         if knn_device is None:
             _lib.check(self._lib.graph_build(xp, x.shape[0], x.shape[1], int(k), int(n0), int(n_threads),
@@ -66,29 +71,77 @@ class Graph:
         else:
             import time
             ts = [time.perf_counter()]
-            _lib.check(self._lib.graph_build_begin(xp, x.shape[0], x.shape[1], int(k), int(n0), int(n_threads),
-                                                   ctypes.byref(handle)), "graph_build_begin")
-            self._h = handle
             n = x.shape[0]
-            nodes = np.empty(n * _lib.KNN_NODE_BYTES, np.uint8)
-            rank_of = np.empty(n, np.int32)
-            _lib.check(self._lib.graph_knn_nodes(self._h, _ptr(nodes), _ptr(rank_of)), "graph_knn_nodes")
             dev = torch.device(knn_device)
+            self.tree_seconds = None
+            if tree_device:
+                x3 = np.zeros((n, 3))
+                x3[:, :x.shape[1]] = x
+                t_tree = time.perf_counter()
+                x_d = torch.from_numpy(x3).to(dev)
+                nb = ctypes.c_size_t()
+                _lib.check(self._lib.graph_tree_scratch_bytes(n, ctypes.byref(nb)), "graph_tree_scratch_bytes")
+                scratch = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+                perm_d = torch.empty(n, dtype=torch.int32, device=dev)
+                sdim_d = torch.empty(n, dtype=torch.int32, device=dev)
+                _lib.check(self._lib.graph_tree_device(ctypes.c_void_p(x_d.data_ptr()), n, x.shape[1],
+                                                       ctypes.c_void_p(perm_d.data_ptr()),
+                                                       ctypes.c_void_p(sdim_d.data_ptr()),
+                                                       ctypes.c_void_p(scratch.data_ptr()), nb.value, _stream(dev)),
+                           "graph_tree_device")
+                perm, sdim = perm_d.cpu().numpy(), sdim_d.cpu().numpy()
+                self.tree_seconds = time.perf_counter() - t_tree
+                del x_d, scratch, perm_d, sdim_d
+                _lib.check(self._lib.graph_build_begin_tree(xp, n, x.shape[1], int(k), int(n0), int(n_threads),
+                                                            _ptr(perm), _ptr(sdim), ctypes.byref(handle)),
+                           "graph_build_begin_tree")
+            else:
+                _lib.check(self._lib.graph_build_begin(xp, x.shape[0], x.shape[1], int(k), int(n0), int(n_threads),
+                                                       ctypes.byref(handle)), "graph_build_begin")
+            self._h = handle
+            # page-locked host buffers: the node and row transfers run at the
+            # link's rate instead of through pageable staging
+            nodes_h = torch.empty(n * _lib.KNN_NODE_BYTES, dtype=torch.uint8, pin_memory=True)
+            rank_h = torch.empty(n, dtype=torch.int32, pin_memory=True)
+            _lib.check(self._lib.graph_knn_nodes(self._h, ctypes.c_void_p(nodes_h.data_ptr()),
+                                                 ctypes.c_void_p(rank_h.data_ptr())), "graph_knn_nodes")
             ts.append(time.perf_counter())
-            nodes_d = torch.from_numpy(nodes).to(dev)
-            rank_d = torch.from_numpy(rank_of).to(dev)
+            nodes_d = nodes_h.to(dev)
+            rank_d = rank_h.to(dev)
             rows_d = torch.empty(max((n - int(n0)) * int(k), 1), dtype=torch.int32, device=dev)
             _lib.check(self._lib.graph_knn_device(ctypes.c_void_p(nodes_d.data_ptr()), ctypes.c_void_p(rank_d.data_ptr()),
                                                   n, x.shape[1], int(k), int(n0), ctypes.c_void_p(rows_d.data_ptr()),
                                                   _stream(dev)), "graph_knn_device")
-            rows = rows_d.cpu().numpy()
+            torch.cuda.synchronize(dev)
             ts.append(time.perf_counter())
-            self.knn_seconds = ts[-1] - ts[-2]
-            del nodes_d, rank_d, rows_d
-            _lib.check(self._lib.graph_build_finish(self._h, _ptr(rows)), "graph_build_finish")
+            depth = None
+            if depth_device:
+                depth_d = torch.empty(n, dtype=torch.int32, device=dev)
+                flag_d = torch.empty(1, dtype=torch.int32, device=dev)
+                sw = ctypes.c_int32()
+                _lib.check(self._lib.graph_depth_device(ctypes.c_void_p(rows_d.data_ptr()), n, int(k), int(n0),
+                                                        ctypes.c_void_p(depth_d.data_ptr()),
+                                                        ctypes.c_void_p(flag_d.data_ptr()), _stream(dev),
+                                                        ctypes.byref(sw)), "graph_depth_device")
+                depth = depth_d.cpu().numpy()
+                self.depth_sweeps = sw.value
             ts.append(time.perf_counter())
-            self.split_seconds = {"begin_and_nodes": ts[1] - ts[0], "device_search": ts[2] - ts[1],
-                                  "finish": ts[3] - ts[2]}
+            rows_h = torch.empty(rows_d.numel(), dtype=torch.int32, pin_memory=True)
+            rows_h.copy_(rows_d)
+            rows = rows_h.numpy()
+            ts.append(time.perf_counter())
+            self.knn_seconds = (ts[2] - ts[1]) + (ts[4] - ts[3])
+            del nodes_d, rank_d, rows_d, nodes_h, rank_h
+            if depth is not None:
+                _lib.check(self._lib.graph_build_finish_depth(self._h, _ptr(rows), _ptr(depth)),
+                           "graph_build_finish_depth")
+            else:
+                _lib.check(self._lib.graph_build_finish(self._h, _ptr(rows)), "graph_build_finish")
+            ts.append(time.perf_counter())
+            self.split_seconds = {"begin_and_nodes": ts[1] - ts[0], "device_tree": self.tree_seconds,
+                                  "device_search": ts[2] - ts[1],
+                                  "device_depth": ts[3] - ts[2], "rows_to_host": ts[4] - ts[3],
+                                  "finish": ts[5] - ts[4]}
         n, d, kk, kp, nn0, nl = (ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(),
                                  ctypes.c_int32(), ctypes.c_int32())
         _lib.check(self._lib.graph_info(self._h, ctypes.byref(n), ctypes.byref(d), ctypes.byref(kk),

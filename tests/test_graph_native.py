@@ -221,3 +221,87 @@ def test_split_build_rejects_bad_rows():
         lib, h = _begin(x, 8, 16)
         assert lib.graph_build_finish(h, ctypes.c_void_p(rows.ctypes.data)) == _lib.EINVAL, mutate
         lib.graph_free(h)
+
+
+def _slot_depths(g):
+    d = np.empty(g.n, np.int32)
+    d[g.slot] = g.depth
+    return d
+
+
+def test_split_build_with_given_depths_equals_graph_build():
+    """graph_build_finish_depth fed the brute-force rows and the host
+    builder's depths (tree slot order) gives the graph of graph_build; a depth
+    that breaks the recurrence is EINVAL."""
+    import ctypes
+    x = np.random.default_rng(21).random((1200, 3))
+    k, n0 = 8, 16
+    og = oracle.build_graph(x, k, n0)
+    ref = Graph(x, k, n0)
+    rows = np.ascontiguousarray(og.nbr.astype(np.int32))
+    depth = _slot_depths(ref)
+    lib, h = _begin(x, k, n0)
+    _lib.check(lib.graph_build_finish_depth(h, ctypes.c_void_p(rows.ctypes.data), ctypes.c_void_p(depth.ctypes.data)),
+               "graph_build_finish_depth")
+    got_order = np.empty(1200, np.int32)
+    got_lp = np.empty(ref.n_levels + 2, np.int32)
+    _lib.check(lib.graph_export(h, ctypes.c_void_p(got_order.ctypes.data), None, ctypes.c_void_p(got_lp.ctypes.data),
+                                None), "graph_export")
+    assert (got_order == ref.order).all() and (got_lp == ref.level_ptr).all()
+    lib.graph_free(h)
+    for i, delta in ((700, 1), (300, -1), (3, 1)):          # a sparse slot one too deep or shallow; a dense one
+        bad = depth.copy()
+        bad[i] += delta
+        lib, h = _begin(x, k, n0)
+        assert lib.graph_build_finish_depth(h, ctypes.c_void_p(rows.ctypes.data), ctypes.c_void_p(bad.ctypes.data)) \
+            == _lib.EINVAL
+        lib.graph_free(h)
+
+
+@pytest.mark.parametrize("n,d,seed", [(1500, 3, 30), (700, 2, 31), (300, 1, 32), (1, 3, 33), (2, 2, 34)])
+def test_begin_from_given_tree_equals_graph_build(n, d, seed):
+    """graph_build_begin_tree fed the oracle's tree (Sec. 2.2) and then the
+    brute-force rows gives the graph of graph_build."""
+    import ctypes
+    x = np.random.default_rng(seed).random((n, d))
+    k, n0 = 8, 1
+    perm, sdim = oracle.tree_order(x)
+    perm, sdim = np.ascontiguousarray(perm.astype(np.int32)), np.ascontiguousarray(sdim.astype(np.int32))
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    xc = np.ascontiguousarray(x)
+    _lib.check(lib.graph_build_begin_tree(xc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n, d, k, n0, 2,
+                                          ctypes.c_void_p(perm.ctypes.data), ctypes.c_void_p(sdim.ctypes.data),
+                                          ctypes.byref(h)), "graph_build_begin_tree")
+    og = oracle.build_graph(x, k, n0)
+    rows = np.ascontiguousarray(og.nbr.astype(np.int32)) if n > n0 else np.zeros(1, np.int32)
+    _lib.check(lib.graph_build_finish(h, ctypes.c_void_p(rows.ctypes.data)), "graph_build_finish")
+    ref = Graph(x, k, n0)
+    got = np.empty(n, np.int32)
+    _lib.check(lib.graph_export(h, ctypes.c_void_p(got.ctypes.data), None, None, None), "graph_export")
+    assert (got == ref.order).all()
+    lib.graph_free(h)
+
+
+def test_begin_from_given_tree_rejects_other_trees():
+    """A tree that is not the one of the points is EINVAL: two slots swapped,
+    a split dimension changed, an index repeated."""
+    import ctypes
+    rng = np.random.default_rng(35)
+    x = rng.random((900, 3)) * np.array([1.0, 0.5, 0.25])
+    perm, sdim = oracle.tree_order(x)
+    lib = _lib.load()
+    xc = np.ascontiguousarray(x)
+    xp = xc.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    cases = []
+    p = perm.copy(); p[[5, 600]] = p[[600, 5]]; cases.append((p, sdim))
+    s = sdim.copy(); s[0] = (s[0] + 1) % 3; cases.append((perm, s))
+    s = sdim.copy(); s[400] = 2 if s[400] != 2 else 1; cases.append((perm, s))
+    p = perm.copy(); p[10] = p[11]; cases.append((p, sdim))
+    p = perm.copy(); p[1], p[2] = p[2], p[1]; cases.append((p, sdim))
+    for p, s in cases:
+        p = np.ascontiguousarray(p.astype(np.int32))
+        s = np.ascontiguousarray(s.astype(np.int32))
+        h = ctypes.c_void_p()
+        assert lib.graph_build_begin_tree(xp, 900, 3, 8, 16, 2, ctypes.c_void_p(p.ctypes.data),
+                                          ctypes.c_void_p(s.ctypes.data), ctypes.byref(h)) == _lib.EINVAL
