@@ -18,8 +18,9 @@ Gaussian Processes with Vecchia's Approximation):
 * ``vecchia``    -- Eq. (1)-(2), the dense initial batch and Alg. 1 (forward),
                     plus the inverse application and log-determinant listed as
                     building blocks in the abstract.
-* ``adjoint``    -- kernel-parameter and white-noise derivatives (Sec. 2.3),
-                    written as closed forms of the conditional formulas.
+* ``adjoint``    -- kernel-parameter, white-noise and coordinate derivatives
+                    (Sec. 2.3), written as closed forms of the conditional
+                    formulas.
 * ``tangent``    -- the forward-mode counterparts (Sec. 2.3: forward and
                     backward derivatives), same closed forms differentiated
                     in a direction.
@@ -30,13 +31,14 @@ headers).  The paper prints no worked numerical example; the figure data
 (batch sizes, KL divergences, timings) are absent, so those quantities are
 "parity unpinned".
 """
-from .covariance import Kernel, EXP, M32, SE, M52, kappa, dkappa_dsigma, dkappa_dell, cov_matrix
+from .covariance import (Kernel, EXP, M32, SE, M52, kappa, dkappa_dsigma, dkappa_dell, dkappa_dr, cov_matrix,
+                         cov_grad_x)
 from .tree import tree_order, tree_level, left_child, right_child, parent
 from .graph import Graph, build_graph, preceding_knn, depths, storage_order
 from .vecchia import (Factor, dense_block, conditional, conditional_joint, factor,
                       forward, forward_sequential, forward_sparse_solve, inverse,
                       logdet, dense_covariance)
-from .adjoint import forward_vjp, inverse_vjp, logdet_vjp, theta_grad
+from .adjoint import forward_vjp, inverse_vjp, logdet_vjp, theta_grad, x_grad
 
 from .tangent import factor_tangent, forward_jvp
 

@@ -26,6 +26,14 @@ conditional formulas of Eq. (2), with F = (I - B)^-1 D as in ``vecchia``:
   S = L0^-T P L0^-1 and K0_bar = (S + S^T)/2 the Cholesky adjoint;
   theta_bar += sum_{p,q} K0_bar_pq dK0_pq.
 
+Coordinates (with_x): at a fixed graph (the order and the neighbour sets are
+piecewise constant in x) the same cotangents k_bar_p = u_p - 2 sbar b_p of
+k_ci, K_bar_pq = sbar b_p b_q - u_p b_q of K_cc and K0_bar of the dense block
+act through d kappa(|x_p - x_q|)/d x_p = kappa'(r) (x_p - x_q)/r on both
+points of every entry: x_bar_{c_p} += k_bar_p g(x_{c_p}, x_i),
+x_bar_i -= the same, x_bar_{c_p} += sum_q K_bar_pq g(x_{c_p}, x_{c_q}),
+x_bar_{c_q} -= the same, and alike for K0.  x_bar is in slot order (N, d).
+
 theta = (sigma, ell).  Pins (tests/test_oracle_adjoint.py): central finite
 differences of the oracle's own forward/inverse/logdet, the adjoint
 dot-product test <v_bar, F xi> = <F^T v_bar, xi>, d logdet / d sigma = 2N/sigma
@@ -34,7 +42,7 @@ without nugget, and in the exact limit d logdet / d ell = tr(K^-1 dK/d ell).
 import numpy as np
 import scipy.linalg
 
-from .covariance import cov_matrix, dkappa_dell, dkappa_dsigma
+from .covariance import cov_grad_x, cov_matrix, dkappa_dell, dkappa_dsigma
 
 
 def _children_scatter(graph, fac, values):
@@ -84,9 +92,40 @@ def theta_grad(graph, fac, kern, b_bar, sigma_bar, k0_bar):
     return out
 
 
-def forward_vjp(graph, fac, kern, xi, v, v_bar, ld_bar=0.0):
+def x_grad(graph, fac, kern, b_bar, sigma_bar, k0_bar):
+    """Cotangent of the coordinates (slot order, N x d) from the same per-point
+    cotangents of b and sigma and the cotangent of K0 as theta_grad."""
+    xs, n0 = graph.xs, graph.n0
+    out = np.zeros_like(xs, dtype=np.float64)
+    for r in range(graph.n - n0):
+        row = graph.nbr[r]
+        ok = row >= 0
+        c = row[ok]
+        if len(c) == 0:
+            continue
+        xc, xi = xs[c], xs[n0 + r][None, :]
+        b = fac.b[r][ok]
+        kcc = cov_matrix(xc, xc, kern, same=True)
+        u = np.linalg.solve(kcc, b_bar[r][ok])
+        sbar = sigma_bar[r] / (2.0 * fac.sigma[r])
+        k_bar = u - 2.0 * sbar * b
+        kcc_bar = sbar * np.outer(b, b) - np.outer(u, b)
+        gk = cov_grad_x(xc, xi, kern)[:, 0, :]           # d k_p / d x_{c_p}
+        np.add.at(out, c, k_bar[:, None] * gk)
+        out[n0 + r] -= np.sum(k_bar[:, None] * gk, axis=0)
+        gkk = cov_grad_x(xc, xc, kern)                   # d K_pq / d x_{c_p}
+        np.add.at(out, c, np.sum(kcc_bar[:, :, None] * gkk, axis=1))
+        np.add.at(out, c, -np.sum(kcc_bar[:, :, None] * gkk, axis=0))
+    x0 = xs[:n0]
+    g0 = cov_grad_x(x0, x0, kern)
+    out[:n0] += np.sum(k0_bar[:, :, None] * g0, axis=1) - np.sum(k0_bar[:, :, None] * g0, axis=0)
+    return out
+
+
+def forward_vjp(graph, fac, kern, xi, v, v_bar, ld_bar=0.0, with_x=False):
     """Cotangents of xi and of (sigma, ell) for the scalar
-    <v_bar, v> + ld_bar * logdet, with v = F xi.  Returns (xi_bar, theta_bar)."""
+    <v_bar, v> + ld_bar * logdet, with v = F xi.  Returns (xi_bar, theta_bar),
+    and the coordinates' cotangent (slot order) third with with_x."""
     n, n0 = graph.n, graph.n0
     xi = np.asarray(xi, dtype=np.float64)
     v = np.asarray(v, dtype=np.float64)
@@ -109,12 +148,16 @@ def forward_vjp(graph, fac, kern, xi, v, v_bar, ld_bar=0.0):
     k0_bar = _cholesky_adjoint(fac.L0, l0_bar)
     if ld_bar != 0.0:
         k0_bar = k0_bar + ld_bar * scipy.linalg.cho_solve((fac.L0, True), np.eye(n0))
+    if with_x:
+        return (xi_bar, theta_grad(graph, fac, kern, b_bar, sigma_bar, k0_bar),
+                x_grad(graph, fac, kern, b_bar, sigma_bar, k0_bar))
     return xi_bar, theta_grad(graph, fac, kern, b_bar, sigma_bar, k0_bar)
 
 
-def inverse_vjp(graph, fac, kern, v, xi, xi_bar):
+def inverse_vjp(graph, fac, kern, v, xi, xi_bar, with_x=False):
     """Cotangents of v and of (sigma, ell) for <xi_bar, xi>, xi = F^-1 v.
-    Returns (v_bar, theta_bar)."""
+    Returns (v_bar, theta_bar), and the coordinates' cotangent third with
+    with_x."""
     n0 = graph.n0
     v = np.asarray(v, dtype=np.float64)
     xi = np.asarray(xi, dtype=np.float64)
@@ -129,13 +172,20 @@ def inverse_vjp(graph, fac, kern, v, xi, xi_bar):
     sigma_bar = -z[n0:] * xi[n0:]
     l0_bar = -np.tril(np.outer(t0, xi[:n0]))
     k0_bar = _cholesky_adjoint(fac.L0, l0_bar)
+    if with_x:
+        return (v_bar, theta_grad(graph, fac, kern, b_bar, sigma_bar, k0_bar),
+                x_grad(graph, fac, kern, b_bar, sigma_bar, k0_bar))
     return v_bar, theta_grad(graph, fac, kern, b_bar, sigma_bar, k0_bar)
 
 
-def logdet_vjp(graph, fac, kern, ld_bar=1.0):
-    """d (ld_bar * logdet) / d (sigma, ell)."""
+def logdet_vjp(graph, fac, kern, ld_bar=1.0, with_x=False):
+    """d (ld_bar * logdet) / d (sigma, ell), and with with_x also
+    d (ld_bar * logdet) / d x (slot order) second."""
     n0 = graph.n0
     b_bar = np.zeros_like(fac.b)
     sigma_bar = 2.0 * ld_bar / fac.sigma
     k0_bar = ld_bar * scipy.linalg.cho_solve((fac.L0, True), np.eye(n0))
+    if with_x:
+        return (theta_grad(graph, fac, kern, b_bar, sigma_bar, k0_bar),
+                x_grad(graph, fac, kern, b_bar, sigma_bar, k0_bar))
     return theta_grad(graph, fac, kern, b_bar, sigma_bar, k0_bar)

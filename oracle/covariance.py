@@ -17,7 +17,11 @@ parameter nu; the half-integer members have the closed forms above.
 
 Derivatives (nugget excluded): d/dsigma = 2 kappa / sigma and
 d/dell = kappa r/ell^2 (EXP), sigma^2 a^2 exp(-a)/ell (M32),
-kappa r^2/ell^3 (SE), sigma^2 a^2 (1 + a) exp(-a) / (3 ell) (M52).
+kappa r^2/ell^3 (SE), sigma^2 a^2 (1 + a) exp(-a) / (3 ell) (M52);
+in the distance, d kappa/dr = -kappa/ell (EXP), -sigma^2 a exp(-a) sqrt(3)/ell
+(M32), -kappa r/ell^2 (SE), -sigma^2 (a/3)(1 + a) exp(-a) sqrt(5)/ell (M52),
+and in a coordinate, d kappa(|x_p - x_q|)/d x_p = kappa'(r) (x_p - x_q)/r,
+taken as 0 where r = 0 (a point with itself; the nugget has no coordinate).
 
 Pins (tests/test_oracle_covariance.py): EXP, M32 and M52 against the general
 Matern form built from scipy.special.kv; SE against scipy.stats.norm.pdf;
@@ -71,6 +75,33 @@ def dkappa_dell(r, kern):
         a = np.sqrt(5.0) * r / kern.ell
         return kern.sigma * kern.sigma * a * a * (1.0 + a) * np.exp(-a) / (3.0 * kern.ell)
     raise ValueError("unknown kernel kind %r" % (kern.kind,))
+
+
+def dkappa_dr(r, kern):
+    r = np.asarray(r, dtype=np.float64)
+    s2 = kern.sigma * kern.sigma
+    if kern.kind == EXP:
+        return -kappa(r, kern) / kern.ell
+    if kern.kind == M32:
+        a = np.sqrt(3.0) * r / kern.ell
+        return -s2 * a * np.exp(-a) * np.sqrt(3.0) / kern.ell
+    if kern.kind == SE:
+        return -kappa(r, kern) * r / (kern.ell * kern.ell)
+    if kern.kind == M52:
+        a = np.sqrt(5.0) * r / kern.ell
+        return -s2 * (a / 3.0) * (1.0 + a) * np.exp(-a) * np.sqrt(5.0) / kern.ell
+    raise ValueError("unknown kernel kind %r" % (kern.kind,))
+
+
+def cov_grad_x(xa, xb, kern):
+    """g[p, q] = d kappa(|xa_p - xb_q|) / d xa_p, shape (m, n, d); the
+    derivative in xb_q is -g[p, q].  Zero where the two points coincide."""
+    xa = np.atleast_2d(np.asarray(xa, dtype=np.float64))
+    xb = np.atleast_2d(np.asarray(xb, dtype=np.float64))
+    diff = xa[:, None, :] - xb[None, :, :]
+    r = np.sqrt(np.sum(diff * diff, axis=-1))
+    scale = np.where(r > 0, dkappa_dr(r, kern) / np.where(r > 0, r, 1.0), 0.0)
+    return scale[:, :, None] * diff
 
 
 def pairwise_r(xa, xb):
