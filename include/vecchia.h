@@ -309,6 +309,26 @@ int vecchia_backward(const vecchia_view* view, const vecchia_kernel* kern,
                      double logdet_bar, void* xi_bar, void* v_bar_out, double* theta_bar,
                      void* scratch, size_t scratch_bytes, void* stream);
 
+/* The same scalar's derivative with respect to the point coordinates
+ * (Sec. 2.3: derivatives of the building blocks), at a fixed graph: the
+ * order and the neighbour sets are piecewise constant in x and are held.
+ * Every covariance entry kappa(|x_p - x_q|) of K_cc, k_ci and the dense block
+ * passes its cotangent to both points through
+ * d kappa / d x_p = kappa'(r) (x_p - x_q) / r (zero for coincident points).
+ *   x_bar (device, N x 3 doubles, storage order, the third column zero for
+ *          d < 3): the cotangent of view->x, in double for both precisions.
+ * Inputs as vecchia_backward (v_bar, xi_bar_in may be NULL).  Each point's
+ * share from the points that condition on it is gathered over the children
+ * lists in a fixed order: the result does not depend on scheduling.
+ * scratch: vecchia_backward_x_scratch_bytes() bytes (the backward's scratch,
+ * the per-point outputs of the sweeps and 24 bytes per neighbour entry),
+ * 256-byte aligned.  Compiled for k <= 32 (EUNSUPPORTED above).  Errors:
+ * EINVAL, ENOMEM (scratch too small), EUNSUPPORTED, EHIP. */
+int vecchia_backward_x_scratch_bytes(const vecchia_view* view, size_t* bytes);
+int vecchia_backward_x(const vecchia_view* view, const vecchia_kernel* kern, const void* xi, const void* v,
+                       const void* v_bar, const void* xi_bar_in, double logdet_bar, double* x_bar, void* scratch,
+                       size_t scratch_bytes, void* stream);
+
 /* vecchia_backward for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
  * the same derivatives, computed by the same kernels, with the scratch taken

@@ -80,6 +80,9 @@ _SIGNATURES = {
     "vecchia_backward_scratch_bytes": (c_int32, [P(ViewStruct), P(c_size_t)]),
     "vecchia_backward": (c_int32, [P(ViewStruct), P(KernelStruct), c_void_p, c_void_p, c_void_p, c_void_p,
                                    c_double, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "vecchia_backward_x_scratch_bytes": (c_int32, [P(ViewStruct), P(c_size_t)]),
+    "vecchia_backward_x": (c_int32, [P(ViewStruct), P(KernelStruct), c_void_p, c_void_p, c_void_p, c_void_p, c_double,
+                                     c_void_p, c_void_p, c_size_t, c_void_p]),
     "vecchia_backward_noalloc_max_bytes": (c_int32, [P(c_size_t)]),
     "vecchia_backward_noalloc": (c_int32, [P(ViewStruct), P(KernelStruct), c_void_p, c_void_p, c_void_p, c_void_p,
                                            c_double, c_void_p, c_void_p, c_void_p, c_void_p]),

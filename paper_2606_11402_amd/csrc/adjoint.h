@@ -57,7 +57,32 @@ struct AdjArgs {
     double sigma_amp;
     double diag;            // K_ii = sigma^2 + nugget
     Cov<double> cov;
+    double* xgrad = nullptr;  // coordinate cotangents (N x 3, storage order), or null: theta only
 };
+
+// kappa(r) and kappa'(r) / r (no nugget), double; the latter is the factor of
+// (x_p - x_q) in d kappa(|x_p - x_q|) / d x_p, zero where the points coincide.
+template <int KIND>
+__device__ __forceinline__ void cov_and_dr(double r2, const Cov<double>& c, double& kap, double& dscale) {
+    if constexpr (KIND == 0) {
+        const double r = sqrt(r2);
+        kap = c.s2 * exp(-r * c.inv_ell);
+        dscale = r > 0.0 ? -kap * c.inv_ell / r : 0.0;
+    } else if constexpr (KIND == 1) {
+        const double a = sqrt(r2) * c.c_m32;
+        const double e = exp(-a);
+        kap = c.s2 * (1.0 + a) * e;
+        dscale = -c.s2 * e * c.c_m32 * c.c_m32;
+    } else if constexpr (KIND == 3) {
+        const double a = sqrt(r2) * c.c_m52;
+        const double e = exp(-a);
+        kap = c.s2 * fma(a, fma(a, 1.0 / 3.0, 1.0), 1.0) * e;
+        dscale = -c.s2 * (1.0 + a) * e * c.c_m52 * c.c_m52 * (1.0 / 3.0);
+    } else {
+        kap = c.s2 * exp(r2 * c.c_se);
+        dscale = 2.0 * c.c_se * kap;
+    }
+}
 
 __device__ __forceinline__ void block_sum2(double& s0, double& s1, double* sh) {
     for (int off = 32; off > 0; off >>= 1) {

@@ -270,6 +270,24 @@ __global__ __launch_bounds__(VECCHIA_N0MAX) void adj_dense_kernel(AdjArgs<TS> a)
         a.theta_dense[0] = acc_s;
         a.theta_dense[1] = acc_l;
     }
+    // coordinates: K0_bar = sym(Y) acts on both points of every entry, so
+    // point i receives sum_j (Y_ij + Y_ji) kappa'(r)/r (x_i - x_j)
+    if (a.xgrad && i < n0) {
+        const double p0 = (double)a.x[i * 3], p1 = (double)a.x[i * 3 + 1], p2 = (double)a.x[i * 3 + 2];
+        double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+        for (int j = 0; j < n0; ++j) {
+            const double q0 = (double)a.x[j * 3], q1 = (double)a.x[j * 3 + 1], q2 = (double)a.x[j * 3 + 2];
+            double kap, ds;
+            cov_and_dr<KIND>(sqdist3(p0, p1, p2, q0, q1, q2), a.cov, kap, ds);
+            const double wgt = j == i ? 0.0 : (X[i * LD + j] + X[j * LD + i]) * ds;
+            g0 = fma(wgt, p0 - q0, g0);
+            g1 = fma(wgt, p1 - q1, g1);
+            g2 = fma(wgt, p2 - q2, g2);
+        }
+        a.xgrad[i * 3] = g0;
+        a.xgrad[i * 3 + 1] = g1;
+        a.xgrad[i * 3 + 2] = g2;
+    }
 }
 
 // ---- theta = sum of the per-block partials (compensated, fixed order) + dense
@@ -365,6 +383,229 @@ static hipError_t backward_t(const BackwardLaunch& p, hipStream_t s) {
     hipLaunchKernelGGL(adj_theta_reduce_kernel, dim3(1), dim3(1024), 0, s, a.theta_part, a.nblocks, a.theta_dense,
                        a.theta_out);
     return hipGetLastError();
+}
+
+// ---- coordinates (at a fixed graph), per sparse point i: with u, sbar and
+// b as in adj_theta_kernel, the cotangents k_bar_p = u_p - 2 sbar b_p of
+// k_ci and K_bar_pq = sbar b_p b_q - u_p b_q of K_cc act through
+// g(x_p, x_q) = kappa'(r)/r (x_p - x_q) = d kappa(|x_p - x_q|) / d x_p:
+//   x_bar_i      -= sum_p k_bar_p g(x_p, x_i)       (written here)
+//   x_bar_{c(p)} += k_bar_p g(x_p, x_i) + sum_q (K_bar_pq + K_bar_qp) g(x_p, x_q)
+// the latter stored per row entry (tiled like b, one array per dimension)
+// and summed into each neighbour by adj_x_gather_kernel over the children
+// lists, in a fixed order.
+template <typename TS, int K, int KIND>
+__global__ __launch_bounds__(kBlock) void adj_x_kernel(AdjArgs<TS> a, double* __restrict__ contrib,
+                                                       int64_t contrib_stride) {
+    constexpr int P = factor_lanes(VECCHIA_FP64, K);
+    constexpr int R = K / P;
+    constexpr int NA = P * R * (R + 1) / 2;
+    constexpr int PTS = kBlock / P;
+    const int tid = threadIdx.x;
+    const int r = tid % P;
+    const int64_t sp_raw = (int64_t)blockIdx.x * PTS + tid / P;
+    const bool live = sp_raw < a.ns;
+    const int64_t sp = live ? sp_raw : a.ns - 1;
+    const int64_t base = (sp >> 6) * (int64_t)K * kTile + (sp & 63);
+    const int64_t s = a.n0 + sp;
+
+    const double sig = (double)a.sigma[sp];
+    double omega = a.vbar ? a.w[s] : 0.0;
+    if (a.xibar_in) omega -= (double)a.xibar_in[s] / sig;
+    const double sigma_bar = omega * (double)a.xi[s] + 2.0 * a.ldbar / sig;
+    const double sbar = sigma_bar / (2.0 * sig);
+
+    double c0[R], c1[R], c2[R];
+    int ok[R];
+    gather_rows<double, TS, K, P>(a.x, a.nbr, base, r, c0, c1, c2, ok);
+    double bq[R], bbar[R];
+    static_for<0, R>([&](auto PI) {
+        constexpr int p = PI;
+        const int32_t j = a.nbr[base + (int64_t)(p * P + r) * kTile];
+        bq[p] = (double)a.b[base + (int64_t)(p * P + r) * kTile];
+        const double vj = (double)a.v[j >= 0 ? j : 0];   // unconditional load, selected below
+        bbar[p] = j >= 0 ? omega * vj : 0.0;
+    });
+
+    double A[NA];
+    assemble_kcc<double, K, P, KIND>(c0, c1, c2, ok, r, a.cov, A);
+    double Dg[R];
+    static_for<0, R>([&](auto PI) {
+        constexpr int p = PI;
+        Dg[p] = ok[p] ? a.diag : 1.0;
+    });
+    double Inv[R];
+    bool bad = false;
+    double minpiv = 1.0;
+    cholesky_kcc<double, K, P>(A, Dg, Inv, r, bad, minpiv);
+    double u[R];
+    static_for<0, R>([&](auto PI) { u[(int)PI] = bbar[(int)PI]; });
+    lower_solve<double, K, P>(A, Inv, u, r);
+    upper_solve<double, K, P>(A, Inv, u, r);
+
+    const TS* xt = a.x + s * 3;
+    const double t0 = (double)xt[0], t1 = (double)xt[1], t2 = (double)xt[2];
+    double own0 = 0.0, own1 = 0.0, own2 = 0.0;
+    double g0[R], g1[R], g2[R];
+    static_for<0, R>([&](auto PI) {
+        constexpr int p = PI;
+        double kap, ds;
+        cov_and_dr<KIND>(sqdist3(c0[p], c1[p], c2[p], t0, t1, t2), a.cov, kap, ds);
+        const double w = ok[p] ? (u[p] - 2.0 * sbar * bq[p]) * ds : 0.0;
+        g0[p] = w * (c0[p] - t0);
+        g1[p] = w * (c1[p] - t1);
+        g2[p] = w * (c2[p] - t2);
+        own0 -= g0[p];
+        own1 -= g1[p];
+        own2 -= g2[p];
+    });
+    static_for<0, K>([&](auto QI) {
+        constexpr int q = QI, pq = q / P, rq = q % P;
+        const double y0 = group_bcast<P, rq>(c0[pq]);
+        const double y1 = group_bcast<P, rq>(c1[pq]);
+        const double y2 = group_bcast<P, rq>(c2[pq]);
+        const int okq = group_bcast<P, rq>(ok[pq]);
+        const double bqq = group_bcast<P, rq>(bq[pq]);
+        const double uq = group_bcast<P, rq>(u[pq]);
+        static_for<0, R>([&](auto PI) {
+            constexpr int p = PI;
+            double kap, ds;
+            cov_and_dr<KIND>(sqdist3(c0[p], c1[p], c2[p], y0, y1, y2), a.cov, kap, ds);
+            const bool use = (ok[p] & okq) != 0 && (p * P + r) != q;
+            const double w = use ? (2.0 * sbar * bq[p] * bqq - u[p] * bqq - uq * bq[p]) * ds : 0.0;
+            g0[p] = fma(w, c0[p] - y0, g0[p]);
+            g1[p] = fma(w, c1[p] - y1, g1[p]);
+            g2[p] = fma(w, c2[p] - y2, g2[p]);
+        });
+    });
+    own0 = group_sum<P>(own0);
+    own1 = group_sum<P>(own1);
+    own2 = group_sum<P>(own2);
+    if (!live) return;
+    static_for<0, R>([&](auto PI) {
+        constexpr int p = PI;
+        const int64_t e = base + (int64_t)(p * P + r) * kTile;
+        contrib[e] = g0[p];
+        contrib[contrib_stride + e] = g1[p];
+        contrib[2 * contrib_stride + e] = g2[p];
+    });
+    if (r == 0) {
+        a.xgrad[s * 3] = own0;
+        a.xgrad[s * 3 + 1] = own1;
+        a.xgrad[s * 3 + 2] = own2;
+    }
+}
+
+// x_bar_j += the stored row contributions of every child entry of j, in the
+// children lists' (ascending) order.
+template <int KP>
+__global__ __launch_bounds__(kBlock) void adj_x_gather_kernel(const int64_t* __restrict__ child_ptr,
+                                                              const int32_t* __restrict__ child,
+                                                              const double* __restrict__ contrib,
+                                                              int64_t contrib_stride, double* __restrict__ xgrad,
+                                                              int64_t n) {
+    constexpr int SH = KP == 8 ? 3 : (KP == 16 ? 4 : (KP == 32 ? 5 : 6));
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j >= n) return;
+    double g0 = xgrad[j * 3], g1 = xgrad[j * 3 + 1], g2 = xgrad[j * 3 + 2];
+    for (int64_t e = child_ptr[j]; e < child_ptr[j + 1]; ++e) {
+        const int32_t packed = child[e];
+        const int64_t sp = packed >> SH;
+        const int m = packed & (KP - 1);
+        const int64_t idx = ((sp >> 6) * KP + m) * kTile + (sp & 63);
+        g0 += contrib[idx];
+        g1 += contrib[contrib_stride + idx];
+        g2 += contrib[2 * contrib_stride + idx];
+    }
+    xgrad[j * 3] = g0;
+    xgrad[j * 3 + 1] = g1;
+    xgrad[j * 3 + 2] = g2;
+}
+
+template <typename TS, int KP, int KIND>
+static hipError_t backward_x_t(const BackwardLaunch& p, double* xgrad, double* contrib, hipStream_t s) {
+    AdjArgs<TS> a;
+    a.x = static_cast<const TS*>(p.x);
+    a.nbr = p.nbr;
+    a.child_ptr = p.child_ptr;
+    a.child = p.child;
+    a.b = static_cast<const TS*>(p.b);
+    a.sigma = static_cast<const TS*>(p.sigma);
+    a.l0 = p.l0;
+    a.xi = static_cast<const TS*>(p.xi);
+    a.v = static_cast<const TS*>(p.v);
+    a.vbar = static_cast<const TS*>(p.vbar);
+    a.xibar_in = static_cast<const TS*>(p.xibar_in);
+    a.w = static_cast<double*>(p.w);
+    a.xibar = static_cast<TS*>(p.xibar);
+    a.vbar_out = static_cast<TS*>(p.vbar_out);
+    a.t0 = p.t0;
+    a.theta_part = p.theta_part;
+    a.theta_dense = p.theta_dense;
+    a.theta_out = p.theta_out;
+    a.n = p.n;
+    a.ns = p.ns;
+    a.n0 = p.n0;
+    a.kp = KP;
+    a.ldbar = p.ldbar;
+    a.sigma_amp = p.kern.sigma;
+    a.diag = p.kern.sigma * p.kern.sigma + p.kern.nugget;
+    a.cov = make_cov<double>(p.kern);
+    a.xgrad = xgrad;
+    constexpr int P = factor_lanes(VECCHIA_FP64, KP);
+    a.nblocks = (p.ns + kBlock / P - 1) / (kBlock / P);
+    const int64_t stride = ((p.ns + kTile - 1) / kTile) * KP * kTile;
+    hipError_t e = hipSuccess;
+    if (p.vbar) {
+        for (int l = p.n_levels; l >= 0; --l) {
+            const int64_t j0 = l == 0 ? 0 : p.level_ptr[l], j1 = l == 0 ? p.n0 : p.level_ptr[l + 1];
+            if (j1 <= j0) continue;
+            if ((e = launch_adj_sweep<TS, KP>(a, j0, j1, s)) != hipSuccess) return e;
+        }
+    }
+    if (p.xibar_in) {
+        hipLaunchKernelGGL((adj_inverse_kernel<TS, KP>), dim3((unsigned)((p.n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                           s, a);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL((adj_dense_inverse_kernel<TS>), dim3(1), dim3(VECCHIA_N0MAX), 0, s, a);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (a.nblocks > 0) {
+        hipLaunchKernelGGL((adj_x_kernel<TS, KP, KIND>), dim3((unsigned)a.nblocks), dim3(kBlock), 0, s, a, contrib,
+                           stride);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((adj_dense_kernel<TS, KIND>), dim3(1), dim3(VECCHIA_N0MAX), 0, s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL((adj_x_gather_kernel<KP>), dim3((unsigned)((p.n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                       p.child_ptr, p.child, contrib, stride, xgrad, p.n);
+    return hipGetLastError();
+}
+
+template <typename TS, int KP>
+static hipError_t backward_x_kind(const BackwardLaunch& p, double* xgrad, double* contrib, hipStream_t s) {
+    switch (p.kern.kind) {
+        case 0: return backward_x_t<TS, KP, 0>(p, xgrad, contrib, s);
+        case 1: return backward_x_t<TS, KP, 1>(p, xgrad, contrib, s);
+        case 2: return backward_x_t<TS, KP, 2>(p, xgrad, contrib, s);
+        case 3: return backward_x_t<TS, KP, 3>(p, xgrad, contrib, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename TS>
+static hipError_t backward_x_width(const BackwardLaunch& p, double* xgrad, double* contrib, hipStream_t s) {
+    switch (p.kp) {
+        case 8: return backward_x_kind<TS, 8>(p, xgrad, contrib, s);
+        case 16: return backward_x_kind<TS, 16>(p, xgrad, contrib, s);
+        case 32: return backward_x_kind<TS, 32>(p, xgrad, contrib, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_backward_x(const BackwardLaunch& p, double* xgrad, double* contrib, hipStream_t s) {
+    return p.precision == VECCHIA_FP32 ? backward_x_width<float>(p, xgrad, contrib, s)
+                                       : backward_x_width<double>(p, xgrad, contrib, s);
 }
 
 template <typename TS, int KP>

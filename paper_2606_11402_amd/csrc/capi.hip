@@ -457,6 +457,75 @@ extern "C" int vecchia_backward(const vecchia_view* view, const vecchia_kernel* 
     return VECCHIA_OK;
 }
 
+extern "C" int vecchia_backward_x_scratch_bytes(const vecchia_view* view, size_t* bytes) {
+    vecchia_clear_error();
+    Layout lay;
+    int rc = check_view(view, &lay, "vecchia_backward_x_scratch_bytes");
+    if (rc) return rc;
+    if (!bytes) return vecchia_set_error(VECCHIA_EINVAL, "vecchia_backward_x_scratch_bytes: bytes is NULL");
+    *bytes = backward_x_scratch(view->n, view->kp, view->n0, view->precision).total;
+    return VECCHIA_OK;
+}
+
+extern "C" int vecchia_backward_x(const vecchia_view* view, const vecchia_kernel* kern, const void* xi, const void* v,
+                                  const void* v_bar, const void* xi_bar_in, double logdet_bar, double* x_bar,
+                                  void* scratch, size_t scratch_bytes, void* stream) {
+    vecchia_clear_error();
+    Layout lay;
+    int rc = check_view(view, &lay, "vecchia_backward_x");
+    if (rc) return rc;
+    if ((rc = check_kernel(kern))) return rc;
+    if (view->kp > 32)
+        return vecchia_set_error(VECCHIA_EUNSUPPORTED, "vecchia_backward_x: compiled for k <= 32, got k=%d", view->k);
+    if (!view->child_ptr || !view->child)
+        return vecchia_set_error(VECCHIA_EINVAL, "vecchia_backward_x: the view needs child_ptr and child");
+    if (!xi || !v || !x_bar || !scratch)
+        return vecchia_set_error(VECCHIA_EINVAL, "vecchia_backward_x: xi, v, x_bar and scratch must be set");
+    if (!std::isfinite(logdet_bar)) return vecchia_set_error(VECCHIA_EINVAL, "vecchia_backward_x: logdet_bar not finite");
+    const BackwardScratch sc = backward_scratch(view->n, view->kp, view->n0, view->precision);
+    const BackwardXScratch sx = backward_x_scratch(view->n, view->kp, view->n0, view->precision);
+    if (scratch_bytes < sx.total)
+        return vecchia_set_error(VECCHIA_ENOMEM, "vecchia_backward_x: scratch has %zu bytes, needs %zu", scratch_bytes,
+                                 sx.total);
+    if (reinterpret_cast<uintptr_t>(scratch) & 255)
+        return vecchia_set_error(VECCHIA_EINVAL, "vecchia_backward_x: scratch must be 256-byte aligned");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* sb = static_cast<char*>(scratch);
+    BackwardLaunch p;
+    p.precision = view->precision;
+    p.kp = view->kp;
+    p.n0 = view->n0;
+    p.n_levels = view->n_levels;
+    p.n = view->n;
+    p.ns = lay.ns;
+    p.level_ptr = view->level_ptr;
+    p.x = view->x;
+    p.xi = xi;
+    p.v = v;
+    p.vbar = v_bar;
+    p.xibar_in = xi_bar_in;
+    p.b = ws<char>(view, lay.b);
+    p.sigma = ws<char>(view, lay.sigma);
+    p.nbr = view->nbr;
+    p.child_ptr = view->child_ptr;
+    p.child = view->child;
+    p.l0 = ws<double>(view, lay.l0);
+    p.w = sb + sc.w;
+    p.xibar = sb + sx.xibar;
+    p.vbar_out = sb + sx.vbar;
+    p.t0 = reinterpret_cast<double*>(sb + sc.t0);
+    p.theta_part = reinterpret_cast<double*>(sb + sc.part);
+    p.theta_dense = reinterpret_cast<double*>(sb + sc.dense);
+    p.theta_out = nullptr;
+    p.ldbar = logdet_bar;
+    p.kern = *kern;
+    hipError_t e = timed("backward_x", s, [&] {
+        return launch_backward_x(p, x_bar, reinterpret_cast<double*>(sb + sx.contrib), s);
+    });
+    if (e != hipSuccess) return hip_fail(e, "vecchia_backward_x");
+    return VECCHIA_OK;
+}
+
 extern "C" int vecchia_fused_workspace_bytes(int64_t n, int32_t k, int32_t n0, int32_t precision, size_t* bytes) {
     if (!bytes) return vecchia_set_error(VECCHIA_EINVAL, "vecchia_fused_workspace_bytes: bytes is NULL");
     if (k < 1) return vecchia_set_error(VECCHIA_EINVAL, "vecchia_fused_workspace_bytes: need k >= 1");

@@ -229,12 +229,21 @@ struct BackwardLaunch {
     vecchia_kernel kern;
 };
 hipError_t launch_backward(const BackwardLaunch& p, hipStream_t stream);
+// The coordinates' cotangent (N x 3 double, storage order) for the same
+// cotangents; contrib: 3 x ceil(Ns/64) x kp x 64 doubles of scratch.  kp <= 32.
+hipError_t launch_backward_x(const BackwardLaunch& p, double* xgrad, double* contrib, hipStream_t stream);
 
 // Scratch of vecchia_backward: w (N doubles), t0 (n0 doubles), theta partials
 // (2 doubles per block of the theta kernel), dense theta (2 doubles).
 struct BackwardScratch {
     size_t w = 0, t0 = 0, part = 0, dense = 0, total = 0;
     int64_t nblocks = 0;
+};
+// Scratch of vecchia_backward_x: that of vecchia_backward, the sweep's and
+// the inverse's per-point outputs (N each, storage type) and the per-entry
+// coordinate contributions (3 x ceil(Ns/64) x kp x 64 doubles).
+struct BackwardXScratch {
+    size_t xibar = 0, vbar = 0, contrib = 0, total = 0;
 };
 inline BackwardScratch backward_scratch(int64_t n, int kp, int n0, int precision) {
     (void)precision;   // the sweep keeps w in double for both storage precisions
@@ -253,6 +262,21 @@ inline BackwardScratch backward_scratch(int64_t n, int kp, int n0, int precision
     off = align256(off + 2 * sizeof(double));
     b.total = off;
     return b;
+}
+
+inline BackwardXScratch backward_x_scratch(int64_t n, int kp, int n0, int precision) {
+    BackwardXScratch x;
+    const size_t esz = precision == VECCHIA_FP32 ? 4 : 8;
+    const int64_t ntiles = (n - n0 + kTile - 1) / kTile;
+    size_t off = backward_scratch(n, kp, n0, precision).total;
+    x.xibar = off;
+    off = align256(off + (size_t)n * esz);
+    x.vbar = off;
+    off = align256(off + (size_t)n * esz);
+    x.contrib = off;
+    off = align256(off + 3 * (size_t)(ntiles > 0 ? ntiles : 1) * kp * kTile * sizeof(double));
+    x.total = off;
+    return x;
 }
 
 constexpr int kLogdetStage = 256;   // first-stage workgroups of the logdet reduction

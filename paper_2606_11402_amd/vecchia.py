@@ -363,6 +363,29 @@ class Factor:
                    "vecchia_backward")
         return xi_bar, v_bar_out, theta
 
+    def backward_x(self, xi, v, v_bar=None, xi_bar_in=None, logdet_bar=0.0, scratch=None):
+        """Derivative of <v_bar, F xi> + <xi_bar_in, F^-1 v> + logdet_bar *
+        logdet with respect to the point coordinates at this graph: a float64
+        device tensor (N, 3) in storage order (the cotangent of the view's x).
+        Needs a DeviceGraph built with with_children=True; k <= 32."""
+        if self.dg.child_ptr is None:
+            raise ValueError("backward_x needs the children lists: to_device(..., with_children=True)")
+        xi = self._vec(xi, "xi")
+        v = self._vec(v, "v")
+        vb = self._vec(v_bar, "v_bar") if v_bar is not None else None
+        xb = self._vec(xi_bar_in, "xi_bar_in") if xi_bar_in is not None else None
+        x_bar = torch.empty((self.dg.n, 3), dtype=torch.float64, device=self.dg.device)
+        nbytes = ctypes.c_size_t()
+        _lib.check(self._lib.vecchia_backward_x_scratch_bytes(ctypes.byref(self.view), ctypes.byref(nbytes)),
+                   "vecchia_backward_x_scratch_bytes")
+        if scratch is None or scratch.numel() < nbytes.value:
+            scratch = torch.empty(nbytes.value, dtype=torch.uint8, device=self.dg.device)
+        ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+        _lib.check(self._lib.vecchia_backward_x(ctypes.byref(self.view), ctypes.byref(self._kc), ptr(xi), ptr(v),
+                                                ptr(vb), ptr(xb), float(logdet_bar), ptr(x_bar), ptr(scratch),
+                                                scratch.numel(), _stream(self.dg.device)), "vecchia_backward_x")
+        return x_bar
+
     def jvp(self, xi, v, xi_dot=None, sigma_dot=0.0, ell_dot=0.0, logdet=True, scratch=None):
         """Forward-mode derivative: (v_dot, logdet_dot or None) of v = F(xi)
         and of the logdet in the direction (xi_dot, sigma_dot, ell_dot); (xi,
