@@ -542,6 +542,7 @@ def adjoint_step(steps, dev):
     t_forward = timed(lambda: fac.forward(xi, out=v), reps)
     t_full = timed(lambda: fac.backward(xi, v, v_bar=vbar, logdet_bar=1.0, scratch=scratch), reps)
     t_theta = timed(lambda: fac.backward(xi, v, logdet_bar=1.0, scratch=scratch), reps)
+    t_x = timed(lambda: fac.backward_x(xi, v, v_bar=vbar, logdet_bar=1.0), reps)
     t_sweep = max(t_full - t_theta, 1e-6)
     ns = w.n - w.n0
     sb = sweep_bytes(w.n, ns, w.k, 4)
@@ -550,7 +551,8 @@ def adjoint_step(steps, dev):
            "step": "factor + forward + reverse sweep + theta kernel", "theta_bar": [float(t) for t in theta.cpu()],
            "parts_ms": {"factor": round(t_factor, 3), "forward": round(t_forward, 3),
                         "backward": round(t_full, 3), "theta_and_dense": round(t_theta, 3),
-                        "sweep": round(t_sweep, 3)},
+                        "sweep": round(t_sweep, 3),
+                        "coordinates_backward_x": round(t_x, 3)},
            "levels": g.n_levels,
            "rooflines": {
                "sweep": {"bound": "hbm", "achieved": round(sb / (t_sweep * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
