@@ -637,15 +637,19 @@ def k16_radial(steps, dev):
 def serving_run(n_requests):
     """A prefix of the serving request stream (N log-uniform in [1e3, 1e6],
     k in {8, 16, 32}, ell ~ U(0.01, 0.2), forward / inverse / logdet, FP32):
-    closed-loop capacity, then Poisson arrivals at 0.7 of it."""
+    closed-loop capacity, then Poisson arrivals at 0.7 of it.  Graphs of at
+    least 2^15 points are built on the GPU (3 GiB of slices for the 14
+    graph workers), smaller ones on the host."""
     import workloads
     from paper_2606_11402_amd.serve import Server, run_stream
     reqs = workloads.request_stream(n_requests, rate=1.0)
     budget = 8 << 30
-    srv = Server(budget, n_streams=8, graph_workers=14)
+    gdev = 3 << 30
+    srv = Server(budget, n_streams=8, graph_workers=14, graph_device_bytes=gdev)
     closed = run_stream(reqs, srv, rate=None)
+    graphs_on_device = srv.stats()["graphs_on_device"]
     srv.close()
-    srv = Server(budget, n_streams=8, graph_workers=14)
+    srv = Server(budget, n_streams=8, graph_workers=14, graph_device_bytes=gdev)
     lam = 0.7 * closed["req_per_s"]
     opened = run_stream(reqs, srv, rate=lam)
     srv.close()
@@ -653,7 +657,8 @@ def serving_run(n_requests):
             "queue_p50_s", "device_p50_s", "device_p99_s", "peak_hbm_bytes")
     log("serving: capacity %.1f req/s, p50 %.3fs p99 %.3fs at 0.7x" % (closed["req_per_s"], opened["latency_p50_s"],
                                                                      opened["latency_p99_s"]))
-    return {"requests": n_requests, "hbm_budget_bytes": budget, "closed_loop": {a: closed[a] for a in keep},
+    return {"requests": n_requests, "hbm_budget_bytes": budget, "graph_device_bytes": gdev,
+            "graphs_on_device_closed_loop": graphs_on_device, "closed_loop": {a: closed[a] for a in keep},
             "open_loop_0.7": dict({a: opened[a] for a in keep}, lambda_req_per_s=lam)}
 
 

@@ -401,6 +401,7 @@ typedef struct vecchia_serve_stats {
     size_t arena_bytes, bytes_in_use, peak_bytes, largest_free;
     int64_t building, queued, running, admitted, completed, failed, rejected, cancelled;
     int64_t peak_running;   /* most requests resident on the device at once */
+    int64_t graphs_on_device; /* graphs built through the device path (serve_set_graph_device) */
 } vecchia_serve_stats;
 
 /* arena: (device) 256-byte aligned buffer of arena_bytes owned by the caller
@@ -414,6 +415,16 @@ typedef struct vecchia_serve_stats {
  * calls and returns its input (host tests of the scheduler). */
 int serve_create(void* arena, size_t arena_bytes, int32_t n_streams, int32_t graph_workers, int32_t graph_threads,
                  int32_t mock, vecchia_server** out);
+
+/* Device graph builds (Sec. 2.3, last paragraph: tree, neighbour search and
+ * depths on the GPU): buffer (device, 256-byte aligned, owned by the caller
+ * and not touched by it while the server lives) is split into one slice per
+ * graph worker; a worker then builds the graph of a request of at least 2^15
+ * points whose device build fits its slice (graph_tree_device,
+ * graph_knn_device, graph_depth_device on a stream of its own, about
+ * 64 N + 4 N k bytes), and every other graph on the host.  The graphs are the
+ * same bit for bit.  NULL turns it off.  EINVAL for a mock server. */
+int serve_set_graph_device(vecchia_server* s, void* buffer, size_t bytes);
 
 /* Device bytes a request of N points needs (coordinates, tiled neighbours,
  * workspace, input, output). */

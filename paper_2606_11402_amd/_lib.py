@@ -39,7 +39,7 @@ class ServeStats(ctypes.Structure):
     _fields_ = [("arena_bytes", c_size_t), ("bytes_in_use", c_size_t), ("peak_bytes", c_size_t),
                 ("largest_free", c_size_t), ("building", c_int64), ("queued", c_int64), ("running", c_int64),
                 ("admitted", c_int64), ("completed", c_int64), ("failed", c_int64), ("rejected", c_int64),
-                ("cancelled", c_int64), ("peak_running", c_int64)]
+                ("cancelled", c_int64), ("peak_running", c_int64), ("graphs_on_device", c_int64)]
 
 
 class ViewStruct(ctypes.Structure):
@@ -109,6 +109,7 @@ _SIGNATURES = {
     "serve_release": (c_int32, [c_void_p, c_int64]),
     "serve_cancel": (c_int32, [c_void_p, c_int64]),
     "serve_stats": (c_int32, [c_void_p, P(ServeStats)]),
+    "serve_set_graph_device": (c_int32, [c_void_p, c_void_p, c_size_t]),
     "serve_destroy": (None, [c_void_p]),
     "vecchia_last_error": (ctypes.c_char_p, []),
     "vecchia_version": (ctypes.c_char_p, []),

@@ -191,14 +191,113 @@ struct vecchia_server {
     int64_t next_id = 1;
     int64_t n_admitted = 0, n_done = 0, n_failed = 0, n_rejected = 0, n_cancelled = 0;
     int64_t peak_running = 0;   // most requests on the device at once
+    // device graph builds (serve_set_graph_device): one slice and one stream per worker
+    char* gdev = nullptr;
+    size_t gslice = 0;
+    std::vector<hipStream_t> wstreams;
+    int64_t n_graph_device = 0;  // graphs built through the device path
 };
 
 namespace {
 
-void build_request(vecchia_server* s, Request* r) {
+// Graphs below this size are built on the host: the device path's fixed
+// costs (transfers, a synchronisation per step) exceed their build time.
+constexpr int64_t kDeviceGraphMin = int64_t(1) << 15;
+
+// Bytes of a worker's slice that the device build of n points needs: the
+// tree phase (coordinates, sort scratch, tree) and, reusing the same bytes,
+// the neighbour phase (nodes, ranks, rows, depths, a flag).
+size_t device_graph_bytes(int64_t n, int k, int n0) {
+    size_t tree = 0;
+    if (graph_tree_scratch_bytes(n, &tree) != VECCHIA_OK) return ~size_t(0);
+    const size_t a = vk::align256((size_t)n * 24) + vk::align256(tree) + 2 * vk::align256((size_t)n * 4);
+    const size_t b = vk::align256((size_t)n * VECCHIA_KNN_NODE_BYTES) + vk::align256((size_t)n * 4) +
+                     vk::align256((size_t)std::max<int64_t>(n - n0, 1) * k * 4) + vk::align256((size_t)n * 4) + 256;
+    return std::max(a, b);
+}
+
+// The graph through the device steps (tree, neighbour search, depths) in the
+// worker's slice, on its stream; the host checks each step's result as in
+// the split build.  Same graph as graph_build, bit for bit.
+int build_graph_device(vecchia_server* s, int wid, Request* r, int threads, vecchia_graph** out) {
+    char* d = s->gdev + (size_t)wid * s->gslice;
+    hipStream_t st = s->wstreams[wid];
+    const int64_t n = r->n;
+    const int k = r->k, n0 = r->n0;
+    size_t tb = 0;
+    int rc = graph_tree_scratch_bytes(n, &tb);
+    if (rc) return rc;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* p = d + off;
+        off += vk::align256(bytes);
+        return p;
+    };
+    double* dx = reinterpret_cast<double*>(take((size_t)n * 24));
+    void* scr = take(tb);
+    int32_t* dperm = reinterpret_cast<int32_t*>(take((size_t)n * 4));
+    int32_t* dsdim = reinterpret_cast<int32_t*>(take((size_t)n * 4));
+    std::vector<int32_t> perm(n), sdim(n);
+    hipError_t e = hipMemcpyAsync(dx, r->x.data(), (size_t)n * 24, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return vecchia_set_error(VECCHIA_EHIP, "serve graph upload: %s", hipGetErrorString(e));
+    if ((rc = graph_tree_device(dx, n, 3, dperm, dsdim, scr, tb, st))) return rc;
+    e = hipMemcpyAsync(perm.data(), dperm, (size_t)n * 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(sdim.data(), dsdim, (size_t)n * 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return vecchia_set_error(VECCHIA_EHIP, "serve graph tree: %s", hipGetErrorString(e));
+    vecchia_graph* g = nullptr;
+    if ((rc = graph_build_begin_tree(r->x.data(), n, 3, k, n0, threads, perm.data(), sdim.data(), &g))) return rc;
+    std::vector<uint8_t> nodes((size_t)n * VECCHIA_KNN_NODE_BYTES);
+    std::vector<int32_t> rank(n), depth(n), rows((size_t)std::max<int64_t>(n - n0, 1) * k);
+    if ((rc = graph_knn_nodes(g, nodes.data(), rank.data()))) {
+        graph_free(g);
+        return rc;
+    }
+    off = 0;                                            // the tree phase's bytes are free again
+    void* dnodes = take(nodes.size());
+    int32_t* drank = reinterpret_cast<int32_t*>(take((size_t)n * 4));
+    int32_t* drows = reinterpret_cast<int32_t*>(take(rows.size() * 4));
+    int32_t* ddepth = reinterpret_cast<int32_t*>(take((size_t)n * 4));
+    int32_t* dflag = reinterpret_cast<int32_t*>(take(4));
+    e = hipMemcpyAsync(dnodes, nodes.data(), nodes.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(drank, rank.data(), (size_t)n * 4, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) rc = vecchia_set_error(VECCHIA_EHIP, "serve graph nodes: %s", hipGetErrorString(e));
+    if (!rc) rc = graph_knn_device(dnodes, drank, n, 3, k, n0, drows, st);
+    int32_t sweeps = 0;
+    if (!rc) rc = graph_depth_device(drows, n, k, n0, ddepth, dflag, st, &sweeps);
+    if (!rc) {
+        e = hipMemcpyAsync(rows.data(), drows, rows.size() * 4, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(depth.data(), ddepth, (size_t)n * 4, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) rc = vecchia_set_error(VECCHIA_EHIP, "serve graph rows: %s", hipGetErrorString(e));
+    }
+    if (!rc) rc = graph_build_finish_depth(g, rows.data(), depth.data());
+    if (rc) {
+        graph_free(g);
+        return rc;
+    }
+    *out = g;
+    return VECCHIA_OK;
+}
+
+void build_request(vecchia_server* s, Request* r, int wid) {
     vecchia_graph* g = nullptr;
     const int threads = (int)std::max<int64_t>(1, std::min<int64_t>(s->graph_threads, r->n >> 16));
-    int rc = graph_build(r->x.data(), r->n, 3, r->k, r->n0, threads, &g);
+    char* gdev;
+    size_t gslice;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        gdev = s->gdev;
+        gslice = s->gslice;
+    }
+    int rc;
+    if (gdev && r->n >= kDeviceGraphMin && device_graph_bytes(r->n, r->k, r->n0) <= gslice) {
+        rc = build_graph_device(s, wid, r, threads, &g);
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (rc == VECCHIA_OK) s->n_graph_device++;
+    } else {
+        rc = graph_build(r->x.data(), r->n, 3, r->k, r->n0, threads, &g);
+    }
     if (rc == VECCHIA_OK) {
         graph_info(g, nullptr, nullptr, nullptr, nullptr, nullptr, &r->n_levels);
         r->order.resize(r->n);
@@ -247,7 +346,7 @@ void build_request(vecchia_server* s, Request* r) {
     s->ready_q.push_back(r);
 }
 
-void worker_main(vecchia_server* s) {
+void worker_main(vecchia_server* s, int wid) {
     for (;;) {
         Request* r = nullptr;
         {
@@ -259,7 +358,7 @@ void worker_main(vecchia_server* s) {
             if (r->state.load() == CANCELLED) continue;
             r->in_build = true;
         }
-        build_request(s, r);
+        build_request(s, r, wid);
     }
 }
 
@@ -349,8 +448,31 @@ extern "C" int serve_create(void* arena, size_t arena_bytes, int32_t n_streams, 
             }
         }
     }
-    for (int w = 0; w < graph_workers; ++w) s->workers.emplace_back(worker_main, s);
+    if (!s->mock) {
+        s->wstreams.resize(graph_workers);
+        for (auto& st : s->wstreams) {
+            hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+            if (e != hipSuccess) {
+                for (auto& q : s->streams) (void)hipStreamDestroy(q);
+                delete s;
+                return vecchia_set_error(VECCHIA_EHIP, "serve_create: %s", hipGetErrorString(e));
+            }
+        }
+    }
+    for (int w = 0; w < graph_workers; ++w) s->workers.emplace_back(worker_main, s, w);
     *out = s;
+    return VECCHIA_OK;
+}
+
+extern "C" int serve_set_graph_device(vecchia_server* s, void* buffer, size_t bytes) {
+    vecchia_clear_error();
+    if (!s) return vecchia_set_error(VECCHIA_EINVAL, "serve_set_graph_device: server is NULL");
+    if (s->mock) return vecchia_set_error(VECCHIA_EINVAL, "serve_set_graph_device: a mock server has no device");
+    if (buffer && (reinterpret_cast<uintptr_t>(buffer) & 255))
+        return vecchia_set_error(VECCHIA_EINVAL, "serve_set_graph_device: buffer must be 256-byte aligned");
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->gdev = static_cast<char*>(buffer);
+    s->gslice = buffer ? (bytes / s->workers.size()) & ~size_t(255) : 0;
     return VECCHIA_OK;
 }
 
@@ -575,6 +697,7 @@ extern "C" int serve_stats(vecchia_server* s, vecchia_serve_stats* out) {
     out->rejected = s->n_rejected;
     out->cancelled = s->n_cancelled;
     out->peak_running = s->peak_running;
+    out->graphs_on_device = s->n_graph_device;
     return VECCHIA_OK;
 }
 
@@ -593,6 +716,8 @@ extern "C" void serve_destroy(vecchia_server* s) {
         if (kv.second->done_ev) (void)hipEventDestroy(kv.second->done_ev);
         free_pinned(*kv.second);
     }
+    for (auto& st : s->wstreams) (void)hipStreamSynchronize(st);
     for (auto& st : s->streams) (void)hipStreamDestroy(st);
+    for (auto& st : s->wstreams) (void)hipStreamDestroy(st);
     delete s;
 }

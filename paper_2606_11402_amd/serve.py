@@ -28,10 +28,16 @@ class Server:
     """One engine over an HBM arena of ``budget`` bytes (a torch tensor the
     server keeps alive), or a host-only mock engine."""
 
-    def __init__(self, budget, n_streams=8, graph_workers=8, graph_threads=8, mock=False, device="cuda:0"):
+    def __init__(self, budget, n_streams=8, graph_workers=8, graph_threads=8, mock=False, device="cuda:0",
+                 graph_device_bytes=0):
+        """graph_device_bytes > 0: a second device buffer of that size, one
+        slice per graph worker, in which the workers build the graphs of large
+        requests on the GPU (serve_set_graph_device); the graphs are the
+        same."""
         self._lib = _lib.load()
         self.mock = mock
         self.arena = None
+        self.graph_buf = None
         ptr = None
         if not mock:
             import torch
@@ -42,6 +48,11 @@ class Server:
                                           ctypes.byref(h)), "serve_create")
         self._h = h
         self.meta = {}
+        if graph_device_bytes and not mock:
+            import torch
+            self.graph_buf = torch.empty(int(graph_device_bytes), dtype=torch.uint8, device=device)
+            _lib.check(self._lib.serve_set_graph_device(self._h, ctypes.c_void_p(self.graph_buf.data_ptr()),
+                                                        int(graph_device_bytes)), "serve_set_graph_device")
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -207,22 +218,26 @@ def main():
     ap.add_argument("--streams", type=int, default=8)
     ap.add_argument("--workers", type=int, default=14)
     ap.add_argument("--load", type=float, nargs="*", default=[0.7])
+    ap.add_argument("--graph-device-gib", type=float, default=3.0,
+                    help="device buffer for graph builds on the GPU (0: every graph on the host)")
     args = ap.parse_args()
+    gdev = int(args.graph_device_gib * (1 << 30))
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     import workloads
     log = lambda *a: print("[serve]", *a, file=sys.stderr, flush=True)
     reqs = workloads.request_stream(args.requests, rate=1.0)
     budget = int(args.budget_gib * (1 << 30))
-    srv = Server(budget, n_streams=args.streams, graph_workers=args.workers)
+    srv = Server(budget, n_streams=args.streams, graph_workers=args.workers, graph_device_bytes=gdev)
     log("closed loop (all requests at t=0)")
     closed = run_stream(reqs, srv, rate=None, log=log)
     mu = closed["req_per_s"]
     out = {"metric": "Vecchia serving: p50/p99 request latency and points/s", "mu_req_per_s": mu,
            "closed_loop": closed, "budget_bytes": budget, "streams": args.streams, "graph_workers": args.workers,
+           "graph_device_bytes": gdev,
            "runs": []}
     for load in args.load:
         srv.close()
-        srv = Server(budget, n_streams=args.streams, graph_workers=args.workers)
+        srv = Server(budget, n_streams=args.streams, graph_workers=args.workers, graph_device_bytes=gdev)
         lam = load * mu
         log("open loop at lambda = %.1f req/s (%.2f mu)" % (lam, load))
         res = run_stream(reqs, srv, rate=lam, log=log)

@@ -33,6 +33,16 @@ extern "C" int vecchia_factor(vecchia_view*, const vecchia_kernel*, void*) { std
 extern "C" int vecchia_forward(const vecchia_view*, const void*, void*, void*) { std::abort(); }
 extern "C" int vecchia_inverse(const vecchia_view*, const void*, void*, void*) { std::abort(); }
 extern "C" int vecchia_logdet(const vecchia_view*, double*, void*) { std::abort(); }
+extern "C" int graph_tree_scratch_bytes(int64_t, size_t*) { std::abort(); }
+extern "C" int graph_tree_device(const double*, int64_t, int32_t, int32_t*, int32_t*, void*, size_t, void*) {
+    std::abort();
+}
+extern "C" int graph_knn_device(const void*, const int32_t*, int64_t, int32_t, int32_t, int32_t, int32_t*, void*) {
+    std::abort();
+}
+extern "C" int graph_depth_device(const int32_t*, int64_t, int32_t, int32_t, int32_t*, int32_t*, void*, int32_t*) {
+    std::abort();
+}
 
 static std::vector<double> points(int64_t n, int d, unsigned seed) {
     std::mt19937_64 rng(seed);

@@ -84,3 +84,34 @@ def test_served_results_match_direct_calls_and_oracle():
     v_or[og.perm] = oracle.forward(og, of, xi.astype(np.float64)[og.perm])
     assert np.max(np.abs(v_srv - v_or)) / np.max(np.abs(v_or)) <= 1e-4
     assert abs(ld_srv - oracle.logdet(of)) <= 1e-4 * abs(oracle.logdet(of))
+
+
+def test_device_graph_builds_give_the_same_results():
+    """Graphs of large requests built on the GPU (serve_set_graph_device)
+    are the host's graphs bit for bit, so every result is identical."""
+    rng = np.random.default_rng(13)
+    reqs = []
+    for i in range(8):
+        n = int(rng.integers(1 << 15, 150000)) if i % 4 else 5000   # one small request stays on the host
+        k = int(rng.choice([8, 16, 32]))
+        op = ["forward", "inverse", "logdet"][i % 3]
+        x = workloads.as_fp32_exact(workloads.uniform(n, 9000 + i))
+        inp = None if op == "logdet" else workloads.white_noise(n, 9100 + i).astype(np.float32)
+        reqs.append((x, k, float(rng.uniform(0.02, 0.1)), op, inp))
+    budget = 4 * Server.request_bytes(150000, 32)
+    out = []
+    for gdev in (0, 1 << 30):
+        srv = Server(budget, n_streams=4, graph_workers=4, graph_device_bytes=gdev)
+        ids = [submit(srv, r) for r in reqs]
+        res = srv.drain()
+        st = srv.stats()
+        srv.close()
+        print("graph device bytes", gdev, "graphs on device", st["graphs_on_device"], flush=True)
+        assert st["failed"] == 0
+        assert st["graphs_on_device"] == (0 if gdev == 0 else sum(r[0].shape[0] >= (1 << 15) for r in reqs))
+        out.append([res[i][0] for i in ids])
+    for a, b, r in zip(out[0], out[1], reqs):
+        if r[3] == "logdet":
+            assert a == b
+        else:
+            assert np.array_equal(a, b)
