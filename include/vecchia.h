@@ -322,8 +322,8 @@ int vecchia_backward(const vecchia_view* view, const vecchia_kernel* kern,
  * lists in a fixed order: the result does not depend on scheduling.
  * scratch: vecchia_backward_x_scratch_bytes() bytes (the backward's scratch,
  * the per-point outputs of the sweeps and 24 bytes per neighbour entry),
- * 256-byte aligned.  Compiled for k <= 32 (EUNSUPPORTED above).  Errors:
- * EINVAL, ENOMEM (scratch too small), EUNSUPPORTED, EHIP. */
+ * 256-byte aligned.  Errors: EINVAL, ENOMEM (scratch too small),
+ * EUNSUPPORTED, EHIP. */
 int vecchia_backward_x_scratch_bytes(const vecchia_view* view, size_t* bytes);
 int vecchia_backward_x(const vecchia_view* view, const vecchia_kernel* kern, const void* xi, const void* v,
                        const void* v_bar, const void* xi_bar_in, double logdet_bar, double* x_bar, void* scratch,

@@ -571,9 +571,13 @@ static hipError_t backward_x_t(const BackwardLaunch& p, double* xgrad, double* c
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (a.nblocks > 0) {
-        hipLaunchKernelGGL((adj_x_kernel<TS, KP, KIND>), dim3((unsigned)a.nblocks), dim3(kBlock), 0, s, a, contrib,
-                           stride);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if constexpr (KP == 64) {
+            if ((e = launch_adj_x_wide<TS>(a, KIND, contrib, stride, s)) != hipSuccess) return e;
+        } else {
+            hipLaunchKernelGGL((adj_x_kernel<TS, KP, KIND>), dim3((unsigned)a.nblocks), dim3(kBlock), 0, s, a,
+                               contrib, stride);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
     }
     hipLaunchKernelGGL((adj_dense_kernel<TS, KIND>), dim3(1), dim3(VECCHIA_N0MAX), 0, s, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -599,6 +603,7 @@ static hipError_t backward_x_width(const BackwardLaunch& p, double* xgrad, doubl
         case 8: return backward_x_kind<TS, 8>(p, xgrad, contrib, s);
         case 16: return backward_x_kind<TS, 16>(p, xgrad, contrib, s);
         case 32: return backward_x_kind<TS, 32>(p, xgrad, contrib, s);
+        case 64: return backward_x_kind<TS, 64>(p, xgrad, contrib, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -475,8 +475,6 @@ extern "C" int vecchia_backward_x(const vecchia_view* view, const vecchia_kernel
     int rc = check_view(view, &lay, "vecchia_backward_x");
     if (rc) return rc;
     if ((rc = check_kernel(kern))) return rc;
-    if (view->kp > 32)
-        return vecchia_set_error(VECCHIA_EUNSUPPORTED, "vecchia_backward_x: compiled for k <= 32, got k=%d", view->k);
     if (!view->child_ptr || !view->child)
         return vecchia_set_error(VECCHIA_EINVAL, "vecchia_backward_x: the view needs child_ptr and child");
     if (!xi || !v || !x_bar || !scratch)

@@ -230,7 +230,7 @@ struct BackwardLaunch {
 };
 hipError_t launch_backward(const BackwardLaunch& p, hipStream_t stream);
 // The coordinates' cotangent (N x 3 double, storage order) for the same
-// cotangents; contrib: 3 x ceil(Ns/64) x kp x 64 doubles of scratch.  kp <= 32.
+// cotangents; contrib: 3 x ceil(Ns/64) x kp x 64 doubles of scratch.
 hipError_t launch_backward_x(const BackwardLaunch& p, double* xgrad, double* contrib, hipStream_t stream);
 
 // Scratch of vecchia_backward: w (N doubles), t0 (n0 doubles), theta partials

@@ -13,7 +13,7 @@ import torch
 import oracle
 import workloads
 from oracle import Kernel, EXP, M32, SE, M52
-from paper_2606_11402_amd import FP32, FP64, Factor, Graph, KernelParams, VecchiaError
+from paper_2606_11402_amd import FP32, FP64, Factor, Graph, KernelParams
 
 pytestmark = pytest.mark.gpu
 
@@ -113,9 +113,30 @@ def test_forward_loss_x_gradient_fp32(kind):
     assert e <= 1e-4
 
 
-def test_width_64_is_unsupported():
-    c = Case(300, 64, 64, Kernel(M32, 1.0, 0.3), FP64, 900)
-    v = c.fac.forward(c.dev(np.zeros(c.g.n)))
-    with pytest.raises(VecchiaError) as ex:
-        c.fac.backward_x(c.dev(np.zeros(c.g.n)), v, logdet_bar=1.0)
-    assert ex.value.code == -4
+@pytest.mark.parametrize("kind", [EXP, M32, SE, M52])
+def test_width_64_forward_and_logdet_x_gradient_fp64(kind):
+    """k = 64 runs on the one-point-per-wave kernel (lane = row)."""
+    c = Case(700, 64, 70, Kernel(kind, 1.0, 0.3, 1e-4 if kind == SE else 0.0), FP64, 900 + kind)
+    xi = c.rng.standard_normal(c.g.n)
+    vbar = c.rng.standard_normal(c.g.n)
+    v = c.fac.forward(c.dev(xi))
+    gx = c.fac.backward_x(c.dev(xi), v, v_bar=c.dev(vbar), logdet_bar=0.8)
+    v_o = oracle.forward(c.og, c.of, c.ora(xi))
+    _, _, gx_o = oracle.forward_vjp(c.og, c.of, c.kern, c.ora(xi), v_o, c.ora(vbar), ld_bar=0.8, with_x=True)
+    e = err(c.to_slots(gx), gx_o)
+    print("forward x_bar k64", kind, e, flush=True)
+    assert e <= 1e-9
+
+
+def test_width_64_inverse_x_gradient_fp32():
+    c = Case(900, 64, 80, Kernel(M32, 1.0, 0.2), FP32, 950)
+    v_in = c.rng.standard_normal(c.g.n)
+    xibar = c.rng.standard_normal(c.g.n)
+    v = c.dev(v_in)
+    xi = c.fac.inverse(v)
+    gx = c.fac.backward_x(xi, v, xi_bar_in=c.dev(xibar))
+    xi_o = oracle.inverse(c.og, c.of, c.ora(v_in))
+    _, _, gx_o = oracle.inverse_vjp(c.og, c.of, c.kern, c.ora(v_in), xi_o, c.ora(xibar), with_x=True)
+    e = err(c.to_slots(gx), gx_o)
+    print("inverse x_bar k64 fp32", e, flush=True)
+    assert e <= 1e-4
