@@ -109,6 +109,6 @@ __device__ __forceinline__ void block_sum2(double& s0, double& s1, double* sh) {
 template <typename TS>
 hipError_t launch_adj_theta_wide(const AdjArgs<TS>& a, int kind, hipStream_t s);
 template <typename TS>
-hipError_t launch_adj_x_wide(const AdjArgs<TS>& a, int kind, double* contrib, int64_t stride, hipStream_t s);
+hipError_t launch_adj_x_wide(const AdjArgs<TS>& a, int kind, double* contrib, hipStream_t s);
 
 }  // namespace vk

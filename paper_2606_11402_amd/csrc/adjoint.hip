@@ -391,12 +391,11 @@ static hipError_t backward_t(const BackwardLaunch& p, hipStream_t s) {
 // g(x_p, x_q) = kappa'(r)/r (x_p - x_q) = d kappa(|x_p - x_q|) / d x_p:
 //   x_bar_i      -= sum_p k_bar_p g(x_p, x_i)       (written here)
 //   x_bar_{c(p)} += k_bar_p g(x_p, x_i) + sum_q (K_bar_pq + K_bar_qp) g(x_p, x_q)
-// the latter stored per row entry (tiled like b, one array per dimension)
+// the latter stored per row entry (tiled like b, a record of 3 doubles each)
 // and summed into each neighbour by adj_x_gather_kernel over the children
 // lists, in a fixed order.
 template <typename TS, int K, int KIND>
-__global__ __launch_bounds__(kBlock) void adj_x_kernel(AdjArgs<TS> a, double* __restrict__ contrib,
-                                                       int64_t contrib_stride) {
+__global__ __launch_bounds__(kBlock) void adj_x_kernel(AdjArgs<TS> a, double* __restrict__ contrib) {
     constexpr int P = factor_lanes(VECCHIA_FP64, K);
     constexpr int R = K / P;
     constexpr int NA = P * R * (R + 1) / 2;
@@ -459,6 +458,10 @@ __global__ __launch_bounds__(kBlock) void adj_x_kernel(AdjArgs<TS> a, double* __
         own1 -= g1[p];
         own2 -= g2[p];
     });
+    // Each unordered pair once: for column q the lane takes its rows below q
+    // (its row blocks from q's block down, in q's own block the lanes after
+    // q's); the pair's term goes to the row with + and to row q with -, the
+    // latter summed over the group and added by q's lane.
     static_for<0, K>([&](auto QI) {
         constexpr int q = QI, pq = q / P, rq = q % P;
         const double y0 = group_bcast<P, rq>(c0[pq]);
@@ -467,16 +470,30 @@ __global__ __launch_bounds__(kBlock) void adj_x_kernel(AdjArgs<TS> a, double* __
         const int okq = group_bcast<P, rq>(ok[pq]);
         const double bqq = group_bcast<P, rq>(bq[pq]);
         const double uq = group_bcast<P, rq>(u[pq]);
-        static_for<0, R>([&](auto PI) {
+        double h0 = 0.0, h1 = 0.0, h2 = 0.0;
+        static_for<pq, R>([&](auto PI) {
             constexpr int p = PI;
             double kap, ds;
             cov_and_dr<KIND>(sqdist3(c0[p], c1[p], c2[p], y0, y1, y2), a.cov, kap, ds);
-            const bool use = (ok[p] & okq) != 0 && (p * P + r) != q;
+            bool use = (ok[p] & okq) != 0;
+            if constexpr (p == pq) use = use && r > rq;
             const double w = use ? (2.0 * sbar * bq[p] * bqq - u[p] * bqq - uq * bq[p]) * ds : 0.0;
-            g0[p] = fma(w, c0[p] - y0, g0[p]);
-            g1[p] = fma(w, c1[p] - y1, g1[p]);
-            g2[p] = fma(w, c2[p] - y2, g2[p]);
+            const double d0 = w * (c0[p] - y0), d1 = w * (c1[p] - y1), d2 = w * (c2[p] - y2);
+            g0[p] += d0;
+            g1[p] += d1;
+            g2[p] += d2;
+            h0 -= d0;
+            h1 -= d1;
+            h2 -= d2;
         });
+        h0 = group_sum<P>(h0);
+        h1 = group_sum<P>(h1);
+        h2 = group_sum<P>(h2);
+        if (r == rq) {
+            g0[pq] += h0;
+            g1[pq] += h1;
+            g2[pq] += h2;
+        }
     });
     own0 = group_sum<P>(own0);
     own1 = group_sum<P>(own1);
@@ -484,10 +501,10 @@ __global__ __launch_bounds__(kBlock) void adj_x_kernel(AdjArgs<TS> a, double* __
     if (!live) return;
     static_for<0, R>([&](auto PI) {
         constexpr int p = PI;
-        const int64_t e = base + (int64_t)(p * P + r) * kTile;
-        contrib[e] = g0[p];
-        contrib[contrib_stride + e] = g1[p];
-        contrib[2 * contrib_stride + e] = g2[p];
+        double* rec = contrib + 3 * (base + (int64_t)(p * P + r) * kTile);
+        rec[0] = g0[p];
+        rec[1] = g1[p];
+        rec[2] = g2[p];
     });
     if (r == 0) {
         a.xgrad[s * 3] = own0;
@@ -502,20 +519,20 @@ template <int KP>
 __global__ __launch_bounds__(kBlock) void adj_x_gather_kernel(const int64_t* __restrict__ child_ptr,
                                                               const int32_t* __restrict__ child,
                                                               const double* __restrict__ contrib,
-                                                              int64_t contrib_stride, double* __restrict__ xgrad,
-                                                              int64_t n) {
+                                                              double* __restrict__ xgrad, int64_t n) {
     constexpr int SH = KP == 8 ? 3 : (KP == 16 ? 4 : (KP == 32 ? 5 : 6));
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (j >= n) return;
     double g0 = xgrad[j * 3], g1 = xgrad[j * 3 + 1], g2 = xgrad[j * 3 + 2];
+#pragma unroll 4
     for (int64_t e = child_ptr[j]; e < child_ptr[j + 1]; ++e) {
         const int32_t packed = child[e];
         const int64_t sp = packed >> SH;
         const int m = packed & (KP - 1);
-        const int64_t idx = ((sp >> 6) * KP + m) * kTile + (sp & 63);
-        g0 += contrib[idx];
-        g1 += contrib[contrib_stride + idx];
-        g2 += contrib[2 * contrib_stride + idx];
+        const double* rec = contrib + 3 * (((sp >> 6) * KP + m) * kTile + (sp & 63));
+        g0 += rec[0];
+        g1 += rec[1];
+        g2 += rec[2];
     }
     xgrad[j * 3] = g0;
     xgrad[j * 3 + 1] = g1;
@@ -554,7 +571,6 @@ static hipError_t backward_x_t(const BackwardLaunch& p, double* xgrad, double* c
     a.xgrad = xgrad;
     constexpr int P = factor_lanes(VECCHIA_FP64, KP);
     a.nblocks = (p.ns + kBlock / P - 1) / (kBlock / P);
-    const int64_t stride = ((p.ns + kTile - 1) / kTile) * KP * kTile;
     hipError_t e = hipSuccess;
     if (p.vbar) {
         for (int l = p.n_levels; l >= 0; --l) {
@@ -572,17 +588,17 @@ static hipError_t backward_x_t(const BackwardLaunch& p, double* xgrad, double* c
     }
     if (a.nblocks > 0) {
         if constexpr (KP == 64) {
-            if ((e = launch_adj_x_wide<TS>(a, KIND, contrib, stride, s)) != hipSuccess) return e;
+            if ((e = launch_adj_x_wide<TS>(a, KIND, contrib, s)) != hipSuccess) return e;
         } else {
             hipLaunchKernelGGL((adj_x_kernel<TS, KP, KIND>), dim3((unsigned)a.nblocks), dim3(kBlock), 0, s, a,
-                               contrib, stride);
+                               contrib);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
     }
     hipLaunchKernelGGL((adj_dense_kernel<TS, KIND>), dim3(1), dim3(VECCHIA_N0MAX), 0, s, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL((adj_x_gather_kernel<KP>), dim3((unsigned)((p.n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                       p.child_ptr, p.child, contrib, stride, xgrad, p.n);
+                       p.child_ptr, p.child, contrib, xgrad, p.n);
     return hipGetLastError();
 }
 

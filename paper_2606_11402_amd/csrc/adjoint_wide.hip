@@ -95,8 +95,7 @@ __global__ __launch_bounds__(kBlock) void adj_theta_wide_kernel(AdjArgs<TS> a) {
 // K_bar_qp) g(x_p, x_q) is summed by lane p over q and stored in the tiled
 // layout for the children gather.
 template <typename TS, int KIND>
-__global__ __launch_bounds__(kBlock) void adj_x_wide_kernel(AdjArgs<TS> a, double* __restrict__ contrib,
-                                                            int64_t contrib_stride) {
+__global__ __launch_bounds__(kBlock) void adj_x_wide_kernel(AdjArgs<TS> a, double* __restrict__ contrib) {
     __shared__ WideLds sh;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t sp_raw = (int64_t)blockIdx.x * kWideWaves + wave;
@@ -151,9 +150,9 @@ __global__ __launch_bounds__(kBlock) void adj_x_wide_kernel(AdjArgs<TS> a, doubl
         g2 = fma(w, c2 - y2, g2);
     });
     if (!live) return;
-    contrib[e] = g0;
-    contrib[contrib_stride + e] = g1;
-    contrib[2 * contrib_stride + e] = g2;
+    contrib[3 * e] = g0;
+    contrib[3 * e + 1] = g1;
+    contrib[3 * e + 2] = g2;
     if (lane == 0) {
         a.xgrad[s * 3] = own0;
         a.xgrad[s * 3 + 1] = own1;
@@ -162,19 +161,19 @@ __global__ __launch_bounds__(kBlock) void adj_x_wide_kernel(AdjArgs<TS> a, doubl
 }
 
 template <typename TS>
-hipError_t launch_adj_x_wide(const AdjArgs<TS>& a, int kind, double* contrib, int64_t stride, hipStream_t s) {
+hipError_t launch_adj_x_wide(const AdjArgs<TS>& a, int kind, double* contrib, hipStream_t s) {
     switch (kind) {
-        case 0: hipLaunchKernelGGL((adj_x_wide_kernel<TS, 0>), dim3((unsigned)a.nblocks), dim3(kBlock), 0, s, a, contrib, stride); break;
-        case 1: hipLaunchKernelGGL((adj_x_wide_kernel<TS, 1>), dim3((unsigned)a.nblocks), dim3(kBlock), 0, s, a, contrib, stride); break;
-        case 2: hipLaunchKernelGGL((adj_x_wide_kernel<TS, 2>), dim3((unsigned)a.nblocks), dim3(kBlock), 0, s, a, contrib, stride); break;
-        case 3: hipLaunchKernelGGL((adj_x_wide_kernel<TS, 3>), dim3((unsigned)a.nblocks), dim3(kBlock), 0, s, a, contrib, stride); break;
+        case 0: hipLaunchKernelGGL((adj_x_wide_kernel<TS, 0>), dim3((unsigned)a.nblocks), dim3(kBlock), 0, s, a, contrib); break;
+        case 1: hipLaunchKernelGGL((adj_x_wide_kernel<TS, 1>), dim3((unsigned)a.nblocks), dim3(kBlock), 0, s, a, contrib); break;
+        case 2: hipLaunchKernelGGL((adj_x_wide_kernel<TS, 2>), dim3((unsigned)a.nblocks), dim3(kBlock), 0, s, a, contrib); break;
+        case 3: hipLaunchKernelGGL((adj_x_wide_kernel<TS, 3>), dim3((unsigned)a.nblocks), dim3(kBlock), 0, s, a, contrib); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-template hipError_t launch_adj_x_wide<float>(const AdjArgs<float>&, int, double*, int64_t, hipStream_t);
-template hipError_t launch_adj_x_wide<double>(const AdjArgs<double>&, int, double*, int64_t, hipStream_t);
+template hipError_t launch_adj_x_wide<float>(const AdjArgs<float>&, int, double*, hipStream_t);
+template hipError_t launch_adj_x_wide<double>(const AdjArgs<double>&, int, double*, hipStream_t);
 
 template <typename TS>
 hipError_t launch_adj_theta_wide(const AdjArgs<TS>& a, int kind, hipStream_t s) {

@@ -230,7 +230,8 @@ struct BackwardLaunch {
 };
 hipError_t launch_backward(const BackwardLaunch& p, hipStream_t stream);
 // The coordinates' cotangent (N x 3 double, storage order) for the same
-// cotangents; contrib: 3 x ceil(Ns/64) x kp x 64 doubles of scratch.
+// cotangents; contrib: scratch of ceil(Ns/64) x kp x 64 records of 3 doubles
+// (one per neighbour entry, in the entries' tiled order).
 hipError_t launch_backward_x(const BackwardLaunch& p, double* xgrad, double* contrib, hipStream_t stream);
 
 // Scratch of vecchia_backward: w (N doubles), t0 (n0 doubles), theta partials
@@ -241,7 +242,7 @@ struct BackwardScratch {
 };
 // Scratch of vecchia_backward_x: that of vecchia_backward, the sweep's and
 // the inverse's per-point outputs (N each, storage type) and the per-entry
-// coordinate contributions (3 x ceil(Ns/64) x kp x 64 doubles).
+// coordinate contributions (ceil(Ns/64) x kp x 64 records of 3 doubles).
 struct BackwardXScratch {
     size_t xibar = 0, vbar = 0, contrib = 0, total = 0;
 };
