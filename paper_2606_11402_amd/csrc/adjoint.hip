@@ -153,25 +153,29 @@ __global__ __launch_bounds__(kBlock) void adj_theta_kernel(AdjArgs<TS> a) {
 
     const TS* xt = a.x + s * 3;
     const double t0 = (double)xt[0], t1 = (double)xt[1], t2 = (double)xt[2];
-    const double inv_amp = 1.0 / a.sigma_amp;
-    double acc_s = 0.0, acc_l = 0.0;
+    // Off the diagonals every covariance entry is kappa, whose sigma
+    // derivative is 2 kappa / sigma: acc_k collects the kappa-weighted terms
+    // and is scaled once at the end.
+    double acc_k = 0.0, acc_l = 0.0;
     static_for<0, R>([&](auto PI) {
         constexpr int p = PI;
         double kap, dl;
         cov_and_dell<KIND>(sqdist3(c0[p], c1[p], c2[p], t0, t1, t2), a.cov, kap, dl);
         const double coef = ok[p] ? (u[p] - 2.0 * sbar * bq[p]) : 0.0;
-        acc_s = fma(coef, 2.0 * kap * inv_amp, acc_s);
+        acc_k = fma(coef, kap, acc_k);
         acc_l = fma(coef, dl, acc_l);
     });
     // sum_{i,j} cw_i b_j dK_ij with cw_i = sbar b_i - u_i over the distinct
-    // entries of the symmetric dK: the diagonal with weight cw_i b_i, each
-    // entry below it with cw_i b_j + cw_j b_i.  For column q the lane takes
-    // its row blocks from q's block down; rows of that block above the
-    // diagonal get weight 0.
+    // entries of the symmetric dK: the diagonal (dK_ii / dsigma = 2 sigma,
+    // dK_ii / dell = 0) with weight cw_i b_i, each entry below it with
+    // cw_i b_j + cw_j b_i.  For column q the lane takes its rows below q: its
+    // row blocks after q's, and in q's block the lanes after q's.
     double cw[R];
+    double acc_d = 0.0;
     static_for<0, R>([&](auto PI) {
         constexpr int p = PI;
         cw[p] = sbar * bq[p] - u[p];
+        acc_d = fma(ok[p] ? cw[p] : 0.0, bq[p], acc_d);
     });
     static_for<0, K>([&](auto QI) {
         constexpr int q = QI, pq = q / P, rq = q % P;
@@ -185,17 +189,14 @@ __global__ __launch_bounds__(kBlock) void adj_theta_kernel(AdjArgs<TS> a) {
             constexpr int p = PI;
             double kap, dl;
             cov_and_dell<KIND>(sqdist3(c0[p], c1[p], c2[p], y0, y1, y2), a.cov, kap, dl);
-            const bool both = (ok[p] & okq) != 0;
-            const int row = p * P + r;
-            const bool same = row == q;
-            const double ds = both ? (same ? 2.0 * a.sigma_amp : 2.0 * kap * inv_amp) : 0.0;
-            const double dll = (both && !same) ? dl : 0.0;
-            double wgt = same ? cw[p] * bqq : fma(cw[p], bqq, cwq * bq[p]);
-            if constexpr (p == pq) wgt = row < q ? 0.0 : wgt;
-            acc_s = fma(wgt, ds, acc_s);
-            acc_l = fma(wgt, dll, acc_l);
+            bool use = (ok[p] & okq) != 0;
+            if constexpr (p == pq) use = use && r > rq;
+            const double wgt = use ? fma(cw[p], bqq, cwq * bq[p]) : 0.0;
+            acc_k = fma(wgt, kap, acc_k);
+            acc_l = fma(wgt, dl, acc_l);
         });
     });
+    double acc_s = fma(acc_k, 2.0 / a.sigma_amp, acc_d * (2.0 * a.sigma_amp));
     acc_s = group_sum<P>(acc_s);
     acc_l = group_sum<P>(acc_l);
     if (r == 0) acc_s = fma(sbar, 2.0 * a.sigma_amp, acc_s);   // dK_ii / dsigma
