@@ -367,7 +367,7 @@ class Factor:
         """Derivative of <v_bar, F xi> + <xi_bar_in, F^-1 v> + logdet_bar *
         logdet with respect to the point coordinates at this graph: a float64
         device tensor (N, 3) in storage order (the cotangent of the view's x).
-        Needs a DeviceGraph built with with_children=True; k <= 32."""
+        Needs a DeviceGraph built with with_children=True."""
         if self.dg.child_ptr is None:
             raise ValueError("backward_x needs the children lists: to_device(..., with_children=True)")
         xi = self._vec(xi, "xi")
