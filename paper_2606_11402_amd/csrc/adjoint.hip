@@ -40,11 +40,21 @@ __global__ __launch_bounds__(kBlock) void adj_sweep_kernel(AdjArgs<TS> a, int64_
     const int64_t jj = live ? j : j_end - 1;       // dead groups mirror a live node and write nothing
     const int64_t e1 = a.child_ptr[jj + 1];
     double acc = 0.0;
-    for (int64_t e = a.child_ptr[jj] + t; e < e1; e += G) {
-        const int32_t packed = a.child[e];
-        const int64_t sp = packed >> SH;
-        const int m = packed & (KP - 1);
-        acc = fma((double)a.b[((sp >> 6) * KP + m) * kTile + (sp & 63)], a.w[a.n0 + sp], acc);
+    // four children per round: their indices, then their b and w, are loaded
+    // together (past the end the loads repeat a valid child and add nothing),
+    // and added in list order
+    for (int64_t e = a.child_ptr[jj] + t; e < e1; e += 4 * G) {
+        int32_t pk[4];
+        static_for<0, 4>([&](auto U) {
+            const int64_t eu = e + (int)U * G;
+            pk[(int)U] = a.child[eu < e1 ? eu : e];
+        });
+        static_for<0, 4>([&](auto U) {
+            const int64_t sp = pk[(int)U] >> SH;
+            const int m = pk[(int)U] & (KP - 1);
+            const double t_bw = fma((double)a.b[((sp >> 6) * KP + m) * kTile + (sp & 63)], a.w[a.n0 + sp], acc);
+            acc = e + (int)U * G < e1 ? t_bw : acc;
+        });
     }
     acc = group_sum<G>(acc) + (double)a.vbar[jj];
     if (live && t == 0) {
