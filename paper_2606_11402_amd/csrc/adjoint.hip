@@ -219,85 +219,126 @@ __global__ __launch_bounds__(kBlock) void adj_theta_kernel(AdjArgs<TS> a) {
     }
 }
 
-// ---- dense block: xibar0 = L0^T w0 and the Cholesky adjoint contribution
+// ---- dense block: xibar0 = L0^T w0 and the Cholesky adjoint contribution.
+// kDenseLanes lanes serve each row (or column): lane u takes the entries
+// l = u, u + 8, ... of every dot product and the group sums them in a fixed
+// butterfly.  The two triangular solves walk L0 column by column from the
+// last; column j is read from LDS while column j - 1 is being loaded.
+constexpr int kDenseLanes = 8;
+constexpr int kDenseThreads = VECCHIA_N0MAX * kDenseLanes;
+
 template <typename TS, int KIND>
-__global__ __launch_bounds__(VECCHIA_N0MAX) void adj_dense_kernel(AdjArgs<TS> a) {
+__global__ __launch_bounds__(kDenseThreads) void adj_dense_kernel(AdjArgs<TS> a) {
     constexpr int LD = VECCHIA_N0MAX + 1;
+    constexpr int T = kDenseLanes;
     __shared__ double X[VECCHIA_N0MAX * LD];
     __shared__ double G[VECCHIA_N0MAX], Z[VECCHIA_N0MAX], H[VECCHIA_N0MAX];
-    __shared__ double sh[2 * (VECCHIA_N0MAX / 64)];
-    const int i = threadIdx.x;
+    __shared__ double Lc[2][VECCHIA_N0MAX];     // one column of L0, double-buffered
+    __shared__ double Pt[VECCHIA_N0MAX][3];     // coordinates of the dense block
+    __shared__ double sh[2 * (kDenseThreads / 64)];
+    const int tid = threadIdx.x;
+    const int i = tid / T, u = tid % T;          // row (or column) i, lane u of its group
     const int n0 = a.n0;
+    const bool row = i < n0;                     // the same for the whole group
     const double* L = a.l0;
-    if (i < n0) {
-        double g = a.vbar ? a.w[i] : 0.0;
-        if (a.xibar_in) g -= a.t0[i];
-        G[i] = g;
-        Z[i] = (double)a.xi[i];
+    if (tid < n0) {
+        double g = a.vbar ? a.w[tid] : 0.0;
+        if (a.xibar_in) g -= a.t0[tid];
+        G[tid] = g;
+        Z[tid] = (double)a.xi[tid];
+        Pt[tid][0] = (double)a.x[tid * 3];
+        Pt[tid][1] = (double)a.x[tid * 3 + 1];
+        Pt[tid][2] = (double)a.x[tid * 3 + 2];
+        Lc[(n0 - 1) & 1][tid] = L[tid * n0 + n0 - 1];
     }
     __syncthreads();
-    if (i < n0) {
+    // h = L0^T g and xibar0 = L0^T w0 (column i of L0)
+    {
         double h = 0.0, xb = 0.0;
-        for (int m = i; m < n0; ++m) {
-            h = fma(L[m * n0 + i], G[m], h);
-            if (a.vbar) xb = fma(L[m * n0 + i], a.w[m], xb);
+        if (row) {
+            for (int m = i + u; m < n0; m += T) {
+                const double l = L[m * n0 + i];
+                h = fma(l, G[m], h);
+                if (a.vbar) xb = fma(l, a.w[m], xb);
+            }
         }
-        H[i] = h;
-        if (a.vbar) a.xibar[i] = (TS)xb;
+        h = group_sum<T>(h);
+        xb = group_sum<T>(xb);
+        if (row && u == 0) {
+            H[i] = h;
+            if (a.vbar) a.xibar[i] = (TS)xb;
+        }
     }
     __syncthreads();
     // X = M L0^-1, row i: x L0 = m  (backward over columns)
-    if (i < n0) {
-        for (int j = n0 - 1; j >= 0; --j) {
-            double m = j < i ? H[i] * Z[j] : (j == i ? 0.5 * H[i] * Z[i] + a.ldbar : 0.0);
-            for (int l = j + 1; l < n0; ++l) m = fma(-X[i * LD + l], L[l * n0 + j], m);
-            X[i * LD + j] = m / L[j * n0 + j];
+    for (int j = n0 - 1; j >= 0; --j) {
+        const double nxt = (j > 0 && tid < n0) ? L[tid * n0 + j - 1] : 0.0;
+        const double* lc = Lc[j & 1];
+        double part = 0.0;
+        if (row)
+            for (int l = j + 1 + u; l < n0; l += T) part = fma(X[i * LD + l], lc[l], part);
+        part = group_sum<T>(part);
+        if (row && u == 0) {
+            const double m = j < i ? H[i] * Z[j] : (j == i ? 0.5 * H[i] * Z[i] + a.ldbar : 0.0);
+            X[i * LD + j] = (m - part) / lc[j];
         }
+        if (j > 0 && tid < n0) Lc[(j - 1) & 1][tid] = nxt;
+        __syncthreads();
     }
-    __syncthreads();
     // Y = L0^-T X, column i: L0^T y = x  (backward over rows), in place
-    if (i < n0) {
-        for (int rr = n0 - 1; rr >= 0; --rr) {
-            double m = X[rr * LD + i];
-            for (int l = rr + 1; l < n0; ++l) m = fma(-L[l * n0 + rr], X[l * LD + i], m);
-            X[rr * LD + i] = m / L[rr * n0 + rr];
-        }
-    }
+    if (tid < n0) Lc[(n0 - 1) & 1][tid] = L[tid * n0 + n0 - 1];
     __syncthreads();
+    for (int rr = n0 - 1; rr >= 0; --rr) {
+        const double nxt = (rr > 0 && tid < n0) ? L[tid * n0 + rr - 1] : 0.0;
+        const double* lc = Lc[rr & 1];
+        double part = 0.0;
+        if (row)
+            for (int l = rr + 1 + u; l < n0; l += T) part = fma(lc[l], X[l * LD + i], part);
+        part = group_sum<T>(part);
+        if (row && u == 0) X[rr * LD + i] = (X[rr * LD + i] - part) / lc[rr];
+        if (rr > 0 && tid < n0) Lc[(rr - 1) & 1][tid] = nxt;
+        __syncthreads();
+    }
     double acc_s = 0.0, acc_l = 0.0;
-    if (i < n0) {
-        const double p0 = (double)a.x[i * 3], p1 = (double)a.x[i * 3 + 1], p2 = (double)a.x[i * 3 + 2];
-        for (int j = 0; j < n0; ++j) {
+    if (row) {
+        const double p0 = Pt[i][0], p1 = Pt[i][1], p2 = Pt[i][2];
+        for (int j = u; j < n0; j += T) {
             double kap, dl;
-            cov_and_dell<KIND>(sqdist3(p0, p1, p2, (double)a.x[j * 3], (double)a.x[j * 3 + 1], (double)a.x[j * 3 + 2]),
-                               a.cov, kap, dl);
+            cov_and_dell<KIND>(sqdist3(p0, p1, p2, Pt[j][0], Pt[j][1], Pt[j][2]), a.cov, kap, dl);
             const double y = X[i * LD + j];
             acc_s = fma(y, i == j ? 2.0 * a.sigma_amp : 2.0 * kap / a.sigma_amp, acc_s);
             acc_l = fma(y, i == j ? 0.0 : dl, acc_l);
         }
     }
     block_sum2(acc_s, acc_l, sh);
-    if (i == 0) {
+    if (tid == 0) {
         a.theta_dense[0] = acc_s;
         a.theta_dense[1] = acc_l;
     }
     // coordinates: K0_bar = sym(Y) acts on both points of every entry, so
     // point i receives sum_j (Y_ij + Y_ji) kappa'(r)/r (x_i - x_j)
-    if (a.xgrad && i < n0) {
-        const double p0 = (double)a.x[i * 3], p1 = (double)a.x[i * 3 + 1], p2 = (double)a.x[i * 3 + 2];
+    if (a.xgrad) {
         double g0 = 0.0, g1 = 0.0, g2 = 0.0;
-        for (int j = 0; j < n0; ++j) {
-            const double q0 = (double)a.x[j * 3], q1 = (double)a.x[j * 3 + 1], q2 = (double)a.x[j * 3 + 2];
-            double kap, ds;
-            cov_and_dr<KIND>(sqdist3(p0, p1, p2, q0, q1, q2), a.cov, kap, ds);
-            const double wgt = j == i ? 0.0 : (X[i * LD + j] + X[j * LD + i]) * ds;
-            g0 = fma(wgt, p0 - q0, g0);
-            g1 = fma(wgt, p1 - q1, g1);
-            g2 = fma(wgt, p2 - q2, g2);
+        if (row) {
+            const double p0 = Pt[i][0], p1 = Pt[i][1], p2 = Pt[i][2];
+            for (int j = u; j < n0; j += T) {
+                const double q0 = Pt[j][0], q1 = Pt[j][1], q2 = Pt[j][2];
+                double kap, ds;
+                cov_and_dr<KIND>(sqdist3(p0, p1, p2, q0, q1, q2), a.cov, kap, ds);
+                const double wgt = j == i ? 0.0 : (X[i * LD + j] + X[j * LD + i]) * ds;
+                g0 = fma(wgt, p0 - q0, g0);
+                g1 = fma(wgt, p1 - q1, g1);
+                g2 = fma(wgt, p2 - q2, g2);
+            }
         }
-        a.xgrad[i * 3] = g0;
-        a.xgrad[i * 3 + 1] = g1;
-        a.xgrad[i * 3 + 2] = g2;
+        g0 = group_sum<T>(g0);
+        g1 = group_sum<T>(g1);
+        g2 = group_sum<T>(g2);
+        if (row && u == 0) {
+            a.xgrad[i * 3] = g0;
+            a.xgrad[i * 3 + 1] = g1;
+            a.xgrad[i * 3 + 2] = g2;
+        }
     }
 }
 
@@ -389,7 +430,7 @@ static hipError_t backward_t(const BackwardLaunch& p, hipStream_t s) {
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
     }
-    hipLaunchKernelGGL((adj_dense_kernel<TS, KIND>), dim3(1), dim3(VECCHIA_N0MAX), 0, s, a);
+    hipLaunchKernelGGL((adj_dense_kernel<TS, KIND>), dim3(1), dim3(kDenseThreads), 0, s, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(adj_theta_reduce_kernel, dim3(1), dim3(1024), 0, s, a.theta_part, a.nblocks, a.theta_dense,
                        a.theta_out);
@@ -606,7 +647,7 @@ static hipError_t backward_x_t(const BackwardLaunch& p, double* xgrad, double* c
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
     }
-    hipLaunchKernelGGL((adj_dense_kernel<TS, KIND>), dim3(1), dim3(VECCHIA_N0MAX), 0, s, a);
+    hipLaunchKernelGGL((adj_dense_kernel<TS, KIND>), dim3(1), dim3(kDenseThreads), 0, s, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL((adj_x_gather_kernel<KP>), dim3((unsigned)((p.n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
                        p.child_ptr, p.child, contrib, xgrad, p.n);
