@@ -238,13 +238,19 @@ int build_graph_device(vecchia_server* s, int wid, Request* r, int threads, vecc
     int32_t* dperm = reinterpret_cast<int32_t*>(take((size_t)n * 4));
     int32_t* dsdim = reinterpret_cast<int32_t*>(take((size_t)n * 4));
     std::vector<int32_t> perm(n), sdim(n);
+    // an error return drains the worker's stream first: copies into this
+    // function's host vectors may still be queued on it
+    auto fail = [&](int code) {
+        (void)hipStreamSynchronize(st);
+        return code;
+    };
     hipError_t e = hipMemcpyAsync(dx, r->x.data(), (size_t)n * 24, hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return vecchia_set_error(VECCHIA_EHIP, "serve graph upload: %s", hipGetErrorString(e));
-    if ((rc = graph_tree_device(dx, n, 3, dperm, dsdim, scr, tb, st))) return rc;
+    if (e != hipSuccess) return fail(vecchia_set_error(VECCHIA_EHIP, "serve graph upload: %s", hipGetErrorString(e)));
+    if ((rc = graph_tree_device(dx, n, 3, dperm, dsdim, scr, tb, st))) return fail(rc);
     e = hipMemcpyAsync(perm.data(), dperm, (size_t)n * 4, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipMemcpyAsync(sdim.data(), dsdim, (size_t)n * 4, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return vecchia_set_error(VECCHIA_EHIP, "serve graph tree: %s", hipGetErrorString(e));
+    if (e != hipSuccess) return fail(vecchia_set_error(VECCHIA_EHIP, "serve graph tree: %s", hipGetErrorString(e)));
     vecchia_graph* g = nullptr;
     if ((rc = graph_build_begin_tree(r->x.data(), n, 3, k, n0, threads, perm.data(), sdim.data(), &g))) return rc;
     std::vector<uint8_t> nodes((size_t)n * VECCHIA_KNN_NODE_BYTES);
@@ -274,7 +280,7 @@ int build_graph_device(vecchia_server* s, int wid, Request* r, int threads, vecc
     if (!rc) rc = graph_build_finish_depth(g, rows.data(), depth.data());
     if (rc) {
         graph_free(g);
-        return rc;
+        return fail(rc);
     }
     *out = g;
     return VECCHIA_OK;
