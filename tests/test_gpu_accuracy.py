@@ -53,7 +53,7 @@ LIMIT_REASON = ("cond(K_cc) reaches ~1e8 on these distributions; the error of th
                 "own factor agrees at the bar (state_xi_inverse)")
 
 
-def judge(errs, precision, caps):
+def assess(errs, precision, caps):
     tol = TOL[precision]
     assert errs["not_pd"] == 0
     for name in ("state_v", "state_xi_inverse", "state_logdet"):
@@ -75,7 +75,7 @@ def test_workload2_radial_m32(precision):
     w = workloads.WORKLOADS[2]
     n = 1 << 15
     errs = measure(w.points(n), w.k, Kernel(w.kind, w.sigma, w.ell, w.nugget), w.xi(n), precision)
-    judge(errs, precision, CAPS_W2[precision])
+    assess(errs, precision, CAPS_W2[precision])
 
 
 @pytest.mark.parametrize("precision", [FP32, FP64])
@@ -83,7 +83,7 @@ def test_workload3_clumped_se(precision):
     w = workloads.WORKLOADS[3]
     n = 1 << 14
     errs = measure(w.points(n), w.k, Kernel(w.kind, w.sigma, w.ell, w.nugget), w.xi(n), precision)
-    judge(errs, precision, CAPS_W3[precision])
+    assess(errs, precision, CAPS_W3[precision])
 
 
 def test_redo_threshold_sweep():

@@ -1,4 +1,4 @@
-"""Pins of the test helpers that judge GPU results (run on the CPU): the
+"""Pins of the test helpers that assess GPU results (run on the CPU): the
 backward error of coefficient rows is at roundoff level for the oracle's own
 coefficients, even where K_cc is ill-conditioned, and large for a
 coefficient row with one wrong entry."""
