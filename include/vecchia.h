@@ -62,17 +62,28 @@ extern "C" {
 
 /* ---- covariance ---------------------------------------------------------- */
 /* Stationary kernel kappa(r) of Sec. 2.1 (forms named by the workloads, and
- * the Matern family with smoothing nu of Fig. 1 at its half-integer members):
+ * the Matern family with smoothing nu of Fig. 1):
  *   kind 0 EXP: sigma^2 exp(-r/ell)                                (nu = 1/2)
  *   kind 1 M32: sigma^2 (1 + sqrt3 r/ell) exp(-sqrt3 r/ell)        (nu = 3/2)
  *   kind 2 SE : sigma^2 exp(-r^2/(2 ell^2))                        (nu -> infinity)
  *   kind 3 M52: sigma^2 (1 + a + a^2/3) exp(-a), a = sqrt5 r/ell   (nu = 5/2)
- * `nugget` is added only on the diagonal (a point with itself). */
+ *   kind 4 MATERN: sigma^2 2^(1-nu)/Gamma(nu) a^nu K_nu(a), a = sqrt(2 nu) r/ell,
+ *          any nu in [VECCHIA_NU_MIN, VECCHIA_NU_MAX] (K_nu the modified Bessel
+ *          function of the second kind; sigma^2 at r = 0).  Supported by
+ *          vecchia_factor on FP64 views with k <= 32 (then forward, inverse and
+ *          logdet, which do not depend on the kernel); the FP32 path, k = 64,
+ *          the fused forward, the tangent and both adjoints return
+ *          VECCHIA_EUNSUPPORTED for it.
+ * `nugget` is added only on the diagonal (a point with itself); `nu` is read
+ * by kind 4 only. */
+#define VECCHIA_NU_MIN 0.25
+#define VECCHIA_NU_MAX 8.0
 typedef struct vecchia_kernel {
     int32_t kind;
     double sigma;
     double ell;
     double nugget;
+    double nu;
 } vecchia_kernel;
 
 /* ---- graph (host, int32) -------------------------------------------------- */

@@ -31,7 +31,7 @@ headers).  The paper prints no worked numerical example; the figure data
 (batch sizes, KL divergences, timings) are absent, so those quantities are
 "parity unpinned".
 """
-from .covariance import (Kernel, EXP, M32, SE, M52, kappa, dkappa_dsigma, dkappa_dell, dkappa_dr, cov_matrix,
+from .covariance import (Kernel, EXP, M32, SE, M52, MATERN, kappa, dkappa_dsigma, dkappa_dell, dkappa_dr, cov_matrix,
                          cov_grad_x)
 from .tree import tree_order, tree_level, left_child, right_child, parent
 from .graph import Graph, build_graph, preceding_knn, depths, storage_order
@@ -43,7 +43,7 @@ from .adjoint import forward_vjp, inverse_vjp, logdet_vjp, theta_grad, x_grad
 from .tangent import factor_tangent, forward_jvp
 
 __all__ = [
-    "Kernel", "EXP", "M32", "SE", "kappa", "dkappa_dsigma", "dkappa_dell", "cov_matrix",
+    "Kernel", "EXP", "M32", "SE", "M52", "MATERN", "kappa", "dkappa_dsigma", "dkappa_dell", "cov_matrix",
     "tree_order", "tree_level", "left_child", "right_child", "parent",
     "Graph", "build_graph", "preceding_knn", "depths", "storage_order",
     "Factor", "dense_block", "conditional", "conditional_joint", "factor", "forward",

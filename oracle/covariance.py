@@ -13,7 +13,13 @@ nugget tau added only where the two arguments are the same point (same index):
 * M52: sigma^2 (1 + a + a^2/3) exp(-a),  a = sqrt(5) r/ell   (Matern nu = 5/2)
 
 The accuracy study of Fig. 1 uses the Matern family with a smoothing
-parameter nu; the half-integer members have the closed forms above.
+parameter nu; the half-integer members have the closed forms above, and
+kind MATERN is the family at any nu (Rasmussen and Williams, Eq. 4.14):
+
+* MATERN: sigma^2 2^(1 - nu) / Gamma(nu) a^nu K_nu(a),  a = sqrt(2 nu) r / ell,
+  with K_nu the modified Bessel function of the second kind
+  (scipy.special.kv) and the limit sigma^2 at r = 0.  Only its value is
+  written here (no parameter or distance derivatives).
 
 Derivatives (nugget excluded): d/dsigma = 2 kappa / sigma and
 d/dell = kappa r/ell^2 (EXP), sigma^2 a^2 exp(-a)/ell (M32),
@@ -25,13 +31,16 @@ taken as 0 where r = 0 (a point with itself; the nugget has no coordinate).
 
 Pins (tests/test_oracle_covariance.py): EXP, M32 and M52 against the general
 Matern form built from scipy.special.kv; SE against scipy.stats.norm.pdf;
-every derivative against a central finite difference.
+every derivative against a central finite difference; MATERN at nu = 1/2,
+3/2 and 5/2 against EXP, M32 and M52, and at other nu against K_nu from a
+quadrature of its integral representation (no Bessel routine).
 """
 from dataclasses import dataclass
 
 import numpy as np
+import scipy.special
 
-EXP, M32, SE, M52 = 0, 1, 2, 3
+EXP, M32, SE, M52, MATERN = 0, 1, 2, 3, 4
 
 
 @dataclass(frozen=True)
@@ -40,6 +49,7 @@ class Kernel:
     sigma: float = 1.0
     ell: float = 1.0
     nugget: float = 0.0
+    nu: float = 0.0          # smoothing of kind MATERN (unused by the others)
 
 
 def kappa(r, kern):
@@ -55,6 +65,12 @@ def kappa(r, kern):
     if kern.kind == M52:
         a = np.sqrt(5.0) * r / kern.ell
         return s2 * (1.0 + a + a * a / 3.0) * np.exp(-a)
+    if kern.kind == MATERN:
+        nu = float(kern.nu)
+        a = np.sqrt(2.0 * nu) * r / kern.ell
+        with np.errstate(invalid="ignore", divide="ignore"):
+            val = s2 * 2.0 ** (1.0 - nu) / scipy.special.gamma(nu) * a ** nu * scipy.special.kv(nu, a)
+        return np.where(a > 0.0, val, s2)
     raise ValueError("unknown kernel kind %r" % (kern.kind,))
 
 

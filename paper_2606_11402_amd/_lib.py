@@ -15,7 +15,7 @@ OK, EINVAL, ENOMEM, ENOTPD, EUNSUPPORTED, EHIP, EBUDGET = 0, -1, -2, -3, -4, -5,
 FP64, FP32 = 0, 1
 KMAX, N0MAX = 64, 128
 KNN_NODE_BYTES = 40
-EXP, M32, SE, M52 = 0, 1, 2, 3
+EXP, M32, SE, M52, MATERN = 0, 1, 2, 3, 4
 
 _NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", ENOTPD: "ENOTPD", EUNSUPPORTED: "EUNSUPPORTED",
           EHIP: "EHIP", EBUDGET: "EBUDGET"}
@@ -32,7 +32,7 @@ class VecchiaError(RuntimeError):
 
 
 class KernelStruct(ctypes.Structure):
-    _fields_ = [("kind", c_int32), ("sigma", c_double), ("ell", c_double), ("nugget", c_double)]
+    _fields_ = [("kind", c_int32), ("sigma", c_double), ("ell", c_double), ("nugget", c_double), ("nu", c_double)]
 
 
 class ServeStats(ctypes.Structure):

@@ -78,10 +78,21 @@ int hip_fail(hipError_t e, const char* where) {
 
 int check_kernel(const vecchia_kernel* k) {
     if (!k) return vecchia_set_error(VECCHIA_EINVAL, "kernel is NULL");
-    if (k->kind < 0 || k->kind > 3) return vecchia_set_error(VECCHIA_EINVAL, "kernel kind %d not in {0,1,2,3}", k->kind);
+    if (k->kind < 0 || k->kind > 4) return vecchia_set_error(VECCHIA_EINVAL, "kernel kind %d not in {0,...,4}", k->kind);
+    if (k->kind == 4 && !(k->nu >= VECCHIA_NU_MIN && k->nu <= VECCHIA_NU_MAX))
+        return vecchia_set_error(VECCHIA_EINVAL, "kernel nu must lie in [%g, %g]", VECCHIA_NU_MIN, VECCHIA_NU_MAX);
     if (!(k->sigma > 0.0) || !std::isfinite(k->sigma)) return vecchia_set_error(VECCHIA_EINVAL, "kernel sigma must be > 0");
     if (!(k->ell > 0.0) || !std::isfinite(k->ell)) return vecchia_set_error(VECCHIA_EINVAL, "kernel ell must be > 0");
     if (!(k->nugget >= 0.0) || !std::isfinite(k->nugget)) return vecchia_set_error(VECCHIA_EINVAL, "kernel nugget must be >= 0");
+    return VECCHIA_OK;
+}
+
+// The general Matern kernel is built into the FP64 factor kernels (k <= 32)
+// only; the entry points with their own kernel evaluations refuse it.
+int check_closed_form(const vecchia_kernel* k, const char* who) {
+    if (k->kind == 4)
+        return vecchia_set_error(VECCHIA_EUNSUPPORTED, "%s: the general Matern kernel is supported by vecchia_factor "
+                                 "on FP64 views with k <= 32 only", who);
     return VECCHIA_OK;
 }
 
@@ -159,6 +170,9 @@ extern "C" int vecchia_factor(vecchia_view* view, const vecchia_kernel* kern, vo
     int rc = check_view(view, &lay, "vecchia_factor");
     if (rc) return rc;
     if ((rc = check_kernel(kern))) return rc;
+    if (kern->kind == 4 && (view->precision != VECCHIA_FP64 || view->kp > 32))
+        return vecchia_set_error(VECCHIA_EUNSUPPORTED, "vecchia_factor: the general Matern kernel needs an FP64 view "
+                                 "with k <= 32");
     hipStream_t s = static_cast<hipStream_t>(stream);
     view->kernel = *kern;
     hipError_t e = timed("factor_dense", s, [&] {
@@ -408,6 +422,7 @@ extern "C" int vecchia_backward(const vecchia_view* view, const vecchia_kernel* 
     int rc = check_view(view, &lay, "vecchia_backward");
     if (rc) return rc;
     if ((rc = check_kernel(kern))) return rc;
+    if ((rc = check_closed_form(kern, "vecchia_backward"))) return rc;
     if (!view->child_ptr || !view->child)
         return vecchia_set_error(VECCHIA_EINVAL, "vecchia_backward: the view needs child_ptr and child");
     if (!xi || !v || !theta_bar || !scratch)
@@ -475,6 +490,7 @@ extern "C" int vecchia_backward_x(const vecchia_view* view, const vecchia_kernel
     int rc = check_view(view, &lay, "vecchia_backward_x");
     if (rc) return rc;
     if ((rc = check_kernel(kern))) return rc;
+    if ((rc = check_closed_form(kern, "vecchia_backward_x"))) return rc;
     if (!view->child_ptr || !view->child)
         return vecchia_set_error(VECCHIA_EINVAL, "vecchia_backward_x: the view needs child_ptr and child");
     if (!xi || !v || !x_bar || !scratch)
@@ -544,6 +560,7 @@ extern "C" int vecchia_forward_fused(const vecchia_view* view, const vecchia_ker
     int rc = check_fused_view(view, &lay, "vecchia_forward_fused");
     if (rc) return rc;
     if ((rc = check_kernel(kern))) return rc;
+    if ((rc = check_closed_form(kern, "vecchia_forward_fused"))) return rc;
     if (!xi || !v) return vecchia_set_error(VECCHIA_EINVAL, "vecchia_forward_fused: xi and v must be set");
     if (xi == v) return vecchia_set_error(VECCHIA_EINVAL, "vecchia_forward_fused: xi and v must not alias");
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -634,6 +651,7 @@ extern "C" int vecchia_forward_jvp(const vecchia_view* view, const vecchia_kerne
     int rc = check_view(view, &lay, "vecchia_forward_jvp");
     if (rc) return rc;
     if ((rc = check_kernel(kern))) return rc;
+    if ((rc = check_closed_form(kern, "vecchia_forward_jvp"))) return rc;
     if (!xi || !v || !v_dot || !scratch)
         return vecchia_set_error(VECCHIA_EINVAL, "vecchia_forward_jvp: xi, v, v_dot and scratch must be set");
     if (v_dot == v || v_dot == xi || (xi_dot && v_dot == xi_dot))

@@ -124,6 +124,10 @@ static hipError_t launch_factor_dense_t(int kind, const void* x, int n0, const v
             hipLaunchKernelGGL((factor_dense_kernel<TX, 3>), dim3(1), dim3(kDenseFactorThreads), 0, s, xp, n0, cov,
                                kern.nugget, l0, ld0, status);
             break;
+        case 4:
+            hipLaunchKernelGGL((factor_dense_kernel<TX, 4>), dim3(1), dim3(kDenseFactorThreads), 0, s, xp, n0, cov,
+                               kern.nugget, l0, ld0, status);
+            break;
         default:
             return hipErrorInvalidValue;
     }

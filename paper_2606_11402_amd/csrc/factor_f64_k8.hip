@@ -9,6 +9,7 @@ hipError_t launch_factor_sparse_f64_k8(const FactorLaunch& a, hipStream_t s) {
         case 1: return launch_factor_sparse_t<double, 8, 1>(a, s);
         case 2: return launch_factor_sparse_t<double, 8, 2>(a, s);
         case 3: return launch_factor_sparse_t<double, 8, 3>(a, s);
+        case 4: return launch_factor_sparse_t<double, 8, 4>(a, s);   // general Matern, FP64 only
         default: return hipErrorInvalidValue;
     }
 }

@@ -14,7 +14,7 @@ import torch
 
 from . import _lib
 
-EXP, M32, SE, M52 = _lib.EXP, _lib.M32, _lib.SE, _lib.M52
+EXP, M32, SE, M52, MATERN = _lib.EXP, _lib.M32, _lib.SE, _lib.M52, _lib.MATERN
 FP64, FP32 = _lib.FP64, _lib.FP32
 _TORCH_DTYPE = {FP64: torch.float64, FP32: torch.float32}
 _NP_DTYPE = {FP64: np.float64, FP32: np.float32}
@@ -22,15 +22,18 @@ _NP_DTYPE = {FP64: np.float64, FP32: np.float32}
 
 @dataclass(frozen=True)
 class KernelParams:
-    """Stationary covariance: kind EXP/M32/SE, amplitude sigma, length scale
-    ell and an absolute nugget on the diagonal."""
+    """Stationary covariance: kind EXP/M32/SE/M52/MATERN, amplitude sigma,
+    length scale ell, an absolute nugget on the diagonal and, for MATERN,
+    the smoothing nu."""
     kind: int
     sigma: float = 1.0
     ell: float = 1.0
     nugget: float = 0.0
+    nu: float = 0.0
 
     def to_c(self):
-        return _lib.KernelStruct(int(self.kind), float(self.sigma), float(self.ell), float(self.nugget))
+        return _lib.KernelStruct(int(self.kind), float(self.sigma), float(self.ell), float(self.nugget),
+                                 float(self.nu))
 
 
 def _ptr(a):

@@ -49,7 +49,8 @@ class Run:
         self.kern = kern
         self.precision = precision
         self.dg = self.g.to_device(precision, device)
-        self.fac = Factor(self.dg, KernelParams(kern.kind, kern.sigma, kern.ell, kern.nugget), redo_log2=redo_log2)
+        self.fac = Factor(self.dg, KernelParams(kern.kind, kern.sigma, kern.ell, kern.nugget, kern.nu),
+                          redo_log2=redo_log2)
         self.dtype = torch.float64 if precision == FP64 else torch.float32
         self.xi_input = xi_input
         if xi_input is not None:

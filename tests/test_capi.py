@@ -36,8 +36,8 @@ def test_abi_sizes_match_binding():
     lib = _lib.load()
     vb, kb = ctypes.c_size_t(), ctypes.c_size_t()
     assert lib.vecchia_abi_sizes(ctypes.byref(vb), ctypes.byref(kb)) == 0
-    assert vb.value == ctypes.sizeof(_lib.ViewStruct) == 128
-    assert kb.value == ctypes.sizeof(_lib.KernelStruct) == 32
+    assert vb.value == ctypes.sizeof(_lib.ViewStruct) == 136
+    assert kb.value == ctypes.sizeof(_lib.KernelStruct) == 40
 
 
 def test_padded_widths():

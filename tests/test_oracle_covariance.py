@@ -56,3 +56,41 @@ def test_nugget_only_on_same_index():
     m = oracle.cov_matrix(x, x, k, same=True)
     assert m[0, 0] == 1.5 and m[1, 1] == 1.5 and m[0, 1] == 1.0
     assert oracle.cov_matrix(x, x, k, deriv="sigma")[0, 0] == 2.0
+
+
+# ---- kind MATERN (any nu): pinned by the closed forms at the half-integers
+# and, elsewhere, by K_nu from a quadrature of its integral representation
+# K_nu(a) = int_0^inf exp(-a cosh t) cosh(nu t) dt (no Bessel routine).
+
+@pytest.mark.parametrize("nu,closed", [(0.5, EXP), (1.5, M32), (2.5, M52)])
+def test_matern_general_at_half_integers_is_the_closed_form(nu, closed):
+    r = np.array([0.0, 1e-6, 0.01, 0.07, 0.3, 0.9, 2.5])
+    gen = oracle.kappa(r, Kernel(oracle.MATERN, 1.4, 0.35, nu=nu))
+    ref = oracle.kappa(r, Kernel(closed, 1.4, 0.35))
+    assert np.allclose(gen, ref, rtol=1e-13, atol=0.0)
+
+
+def _k_nu_quadrature(nu, a):
+    import scipy.integrate
+    f = lambda t: np.exp(-a * np.cosh(t)) * np.cosh(nu * t)
+    upper = np.arccosh(max(1.0, 800.0 / a)) + 1.0
+    val, _ = scipy.integrate.quad(f, 0.0, upper, epsabs=0.0, epsrel=1e-13, limit=400)
+    return val
+
+
+@pytest.mark.parametrize("nu", [0.3, 0.8, 1.0, 2.2, 3.7, 7.5])
+def test_matern_general_against_integral_representation(nu):
+    kern = Kernel(oracle.MATERN, 0.9, 0.2, nu=nu)
+    for r in (0.003, 0.05, 0.2, 0.6):
+        a = np.sqrt(2.0 * nu) * r / kern.ell
+        ref = kern.sigma ** 2 * 2.0 ** (1.0 - nu) / scipy.special.gamma(nu) * a ** nu * _k_nu_quadrature(nu, a)
+        assert float(oracle.kappa(r, kern)) == pytest.approx(ref, rel=1e-10)
+
+
+def test_matern_general_limit_and_monotone_decay():
+    kern = Kernel(oracle.MATERN, 1.2, 0.3, nu=1.3)
+    r = np.linspace(0.0, 2.0, 400)
+    k = oracle.kappa(r, kern)
+    assert k[0] == kern.sigma ** 2
+    assert abs(k[1] - k[0]) < 1e-3 * k[0]                 # continuous at 0
+    assert np.all(np.diff(k) < 0.0)
