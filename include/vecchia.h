@@ -70,9 +70,10 @@ extern "C" {
  *   kind 4 MATERN: sigma^2 2^(1-nu)/Gamma(nu) a^nu K_nu(a), a = sqrt(2 nu) r/ell,
  *          any nu in [VECCHIA_NU_MIN, VECCHIA_NU_MAX] (K_nu the modified Bessel
  *          function of the second kind; sigma^2 at r = 0).  Supported by
- *          vecchia_factor on FP64 views with k <= 32 (then forward, inverse and
- *          logdet, which do not depend on the kernel); the FP32 path, k = 64,
- *          the fused forward, the tangent and both adjoints return
+ *          vecchia_factor on FP64 views and at k = 64 on both precisions (the
+ *          factors that evaluate covariances in double; then forward, inverse
+ *          and logdet, which do not depend on the kernel); the FP32 factor at
+ *          k <= 32, the fused forward, the tangent and both adjoints return
  *          VECCHIA_EUNSUPPORTED for it.
  * `nugget` is added only on the diagonal (a point with itself); `nu` is read
  * by kind 4 only. */

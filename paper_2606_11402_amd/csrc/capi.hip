@@ -87,12 +87,13 @@ int check_kernel(const vecchia_kernel* k) {
     return VECCHIA_OK;
 }
 
-// The general Matern kernel is built into the FP64 factor kernels (k <= 32)
-// only; the entry points with their own kernel evaluations refuse it.
+// The general Matern kernel is built into the factor kernels that evaluate
+// covariances in double (FP64 views, and k = 64 for both precisions) only;
+// the entry points with their own kernel evaluations refuse it.
 int check_closed_form(const vecchia_kernel* k, const char* who) {
     if (k->kind == 4)
         return vecchia_set_error(VECCHIA_EUNSUPPORTED, "%s: the general Matern kernel is supported by vecchia_factor "
-                                 "on FP64 views with k <= 32 only", who);
+                                 "(FP64 views, or k = 64) only", who);
     return VECCHIA_OK;
 }
 
@@ -170,9 +171,9 @@ extern "C" int vecchia_factor(vecchia_view* view, const vecchia_kernel* kern, vo
     int rc = check_view(view, &lay, "vecchia_factor");
     if (rc) return rc;
     if ((rc = check_kernel(kern))) return rc;
-    if (kern->kind == 4 && (view->precision != VECCHIA_FP64 || view->kp > 32))
+    if (kern->kind == 4 && view->precision != VECCHIA_FP64 && view->kp != 64)
         return vecchia_set_error(VECCHIA_EUNSUPPORTED, "vecchia_factor: the general Matern kernel needs an FP64 view "
-                                 "with k <= 32");
+                                 "or k = 64 (whose factor is in FP64 for both storage precisions)");
     hipStream_t s = static_cast<hipStream_t>(stream);
     view->kernel = *kern;
     hipError_t e = timed("factor_dense", s, [&] {

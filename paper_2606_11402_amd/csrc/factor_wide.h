@@ -207,6 +207,7 @@ hipError_t launch_factor_wide_t(const FactorLaunch& L, hipStream_t stream) {
         case 1: hipLaunchKernelGGL((factor_wide_kernel<TS, 1>), dim3((unsigned)a.nblocks), dim3(kBlock), 0, stream, a, cov); break;
         case 2: hipLaunchKernelGGL((factor_wide_kernel<TS, 2>), dim3((unsigned)a.nblocks), dim3(kBlock), 0, stream, a, cov); break;
         case 3: hipLaunchKernelGGL((factor_wide_kernel<TS, 3>), dim3((unsigned)a.nblocks), dim3(kBlock), 0, stream, a, cov); break;
+        case 4: hipLaunchKernelGGL((factor_wide_kernel<TS, 4>), dim3((unsigned)a.nblocks), dim3(kBlock), 0, stream, a, cov); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -5,7 +5,8 @@ forms at nu = 1/2, 3/2, 5/2 and by quadrature of K_nu's integral
 representation elsewhere), at the FP64 bar 1e-10: coefficients, forward,
 inverse, round trip and logdet, plus the oracle's level operations on the
 GPU's own factor.  The points are uniform with ell = 0.1 (cond(K_cc) at most
-~7e3 over these nu and k), so no metric is conditioning-limited.  At
+~7e3 over these nu and k), so no metric is conditioning-limited.  k = 64
+factors in double for both storage precisions.  At
 nu = 3/2 the general evaluation reproduces the closed-form kind on the GPU;
 the entry points without a general-nu evaluation refuse the kernel."""
 import numpy as np
@@ -55,6 +56,29 @@ def test_general_matern_fp64_against_oracle(nu, k):
         assert e <= TOL, (name, e)
 
 
+@pytest.mark.parametrize("precision", [FP64, FP32])
+def test_general_matern_width_64(precision):
+    """k = 64 factors in double for both storage precisions (one point per
+    wave); FP32 storage of b, sigma and v is judged at the FP32 bar 1e-4."""
+    n = 1500
+    x = workloads.uniform(n, 90)
+    if precision == FP32:
+        x = workloads.as_fp32_exact(x)
+    xi_in = workloads.white_noise(n, 190)
+    kern = Kernel(MATERN, 1.0, 0.1, 1e-8, nu=2.2)
+    run = Run(x, 64, 128, kern, precision, xi_in)
+    ref = oracle_run(x, 64, 128, kern, xi_in)
+    b, s = run.coefficients_by_slot()
+    tol = TOL if precision == FP64 else 1e-4
+    errs = {"b": rel_err(b, ref["fac"].b), "sigma": rel_err(s, ref["fac"].sigma),
+            "v": rel_err(run.slot_order(run.v.cpu().numpy()), ref["v"]),
+            "logdet": abs(run.ld.item() - ref["logdet"]) / abs(ref["logdet"])}
+    print("matern k64", precision, errs, flush=True)
+    assert run.fac.counts()[0] == 0
+    for name, e in errs.items():
+        assert e <= tol, (name, e)
+
+
 @pytest.mark.parametrize("k", [8, 32])
 def test_general_matern_at_three_halves_matches_closed_form_kind(k):
     n = 900
@@ -75,11 +99,8 @@ def test_general_matern_is_refused_where_it_is_not_built():
     x = workloads.as_fp32_exact(workloads.uniform(n, 80))
     kp = KernelParams(MATERN, 1.0, 0.1, 0.0, 1.3)
     g = Graph(x, 16, 64)
-    with pytest.raises(VecchiaError) as ex:                  # FP32 path
+    with pytest.raises(VecchiaError) as ex:                  # FP32 path at k <= 32
         Factor(g.to_device(FP32, "cuda:0"), kp)
-    assert ex.value.code == -4
-    with pytest.raises(VecchiaError) as ex:                  # k = 64
-        Factor(Graph(x, 64, 64).to_device(FP64, "cuda:0"), kp)
     assert ex.value.code == -4
     with pytest.raises(VecchiaError) as ex:                  # nu outside [1/4, 8]
         Factor(g.to_device(FP64, "cuda:0"), KernelParams(MATERN, 1.0, 0.1, 0.0, 9.0))
