@@ -381,6 +381,7 @@ def main():
         del v32
         torch.cuda.empty_cache()
         out["k16_radial"] = k16_radial(args.steps, dev)
+        out["matern_general_nu"] = matern_general(args.steps, dev)
         if args.workload == 3 and args.k is None:
             out["k16_same_distribution"] = same_distribution_k16(w, n, args.steps, dev, args.threads)
         out["adjoint_radial_2e22"] = adjoint_step(args.steps, dev)
@@ -631,6 +632,36 @@ def k16_radial(steps, dev):
                            "logdet_rel": abs(l32 - l64) / abs(l64)}
     res["config"] = {"workload": w.name, "n": w.n, "k": w.k, "kernel": "M32", "ell": w.ell}
     log("k16 radial:", res)
+    return res
+
+
+def matern_general(steps, dev):
+    """Cost of the general Matern kernel (kind 4, K_nu evaluated per entry)
+    against the closed-form Matern-3/2 on the same graph: 2^20 uniform
+    points, k = 16, ell = 0.02, FP64 path, factor + forward + logdet; and at
+    nu = 3/2 the general kernel's results against the closed form's."""
+    import torch
+    import workloads
+    from paper_2606_11402_amd import FP64, M32, MATERN, Factor, Graph, KernelParams
+    n, k, n0 = 1 << 20, 16, 128
+    g = Graph(workloads.uniform(n, 2026), k, n0, knn_device=dev)
+    dg = g.to_device(FP64, dev)
+    xi = torch.from_numpy(g.to_storage(workloads.white_noise(n, 2126))).to(dg.dtype).to(dev)
+    res, outs = {"config": {"workload": "uniform-2^20-k16-fp64", "n": n, "k": k, "ell": 0.02}}, {}
+    for name, kern in (("m32", KernelParams(M32, 1.0, 0.02)), ("matern_nu_1.5", KernelParams(MATERN, 1.0, 0.02, 0.0, 1.5)),
+                       ("matern_nu_1.7", KernelParams(MATERN, 1.0, 0.02, 0.0, 1.7))):
+        v = torch.empty(n, dtype=dg.dtype, device=dev)
+        ld = torch.empty(1, dtype=torch.float64, device=dev)
+        fac = Factor(dg, kern)
+        ms = time_steps(fac, xi, v, ld, steps)
+        fac.status()
+        res[name] = {"ms_per_step": round(ms, 3), "points_per_s": n / (ms * 1e-3)}
+        outs[name] = (v.clone(), float(ld.item()))
+        del fac
+    (va, la), (vb, lb) = outs["matern_nu_1.5"], outs["m32"]
+    res["nu_1.5_vs_m32"] = {"v_rel": float(((va - vb).abs().max() / vb.abs().max()).item()),
+                            "logdet_rel": abs(la - lb) / abs(lb)}
+    log("general Matern:", res)
     return res
 
 
