@@ -10,6 +10,7 @@
 #include "fused_kernel.h"
 #include "status.h"
 #include "tangent.h"
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 using namespace vk;
 
@@ -75,6 +76,15 @@ hipError_t timed(const char* name, hipStream_t s, F&& launch) {
 int hip_fail(hipError_t e, const char* where) {
     return vecchia_set_error(VECCHIA_EHIP, "%s: %s", where, hipGetErrorString(e));
 }
+
+// A named roctx range around each call of the path (shown by a marker trace,
+// e.g. rocprofv3 --marker-trace; a flag check when no tool is attached).
+struct TraceRange {
+    explicit TraceRange(const char* name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange&) = delete;
+    TraceRange& operator=(const TraceRange&) = delete;
+};
 
 int check_kernel(const vecchia_kernel* k) {
     if (!k) return vecchia_set_error(VECCHIA_EINVAL, "kernel is NULL");
@@ -167,6 +177,7 @@ extern "C" int vecchia_workspace_bytes(int64_t n, int32_t k, int32_t n0, int32_t
 
 extern "C" int vecchia_factor(vecchia_view* view, const vecchia_kernel* kern, void* stream) {
     vecchia_clear_error();
+    TraceRange trace_range("vecchia_factor");
     Layout lay;
     int rc = check_view(view, &lay, "vecchia_factor");
     if (rc) return rc;
@@ -223,6 +234,7 @@ extern "C" int vecchia_factor(vecchia_view* view, const vecchia_kernel* kern, vo
 
 extern "C" int vecchia_forward(const vecchia_view* view, const void* xi, void* v, void* stream) {
     vecchia_clear_error();
+    TraceRange trace_range("vecchia_forward");
     Layout lay;
     int rc = check_view(view, &lay, "vecchia_forward");
     if (rc) return rc;
@@ -275,6 +287,7 @@ extern "C" int vecchia_forward(const vecchia_view* view, const void* xi, void* v
 
 extern "C" int vecchia_inverse(const vecchia_view* view, const void* v, void* xi, void* stream) {
     vecchia_clear_error();
+    TraceRange trace_range("vecchia_inverse");
     Layout lay;
     int rc = check_view(view, &lay, "vecchia_inverse");
     if (rc) return rc;
@@ -295,6 +308,7 @@ extern "C" int vecchia_inverse(const vecchia_view* view, const void* v, void* xi
 
 extern "C" int vecchia_logdet(const vecchia_view* view, double* out, void* stream) {
     vecchia_clear_error();
+    TraceRange trace_range("vecchia_logdet");
     Layout lay;
     int rc = check_view(view, &lay, "vecchia_logdet");
     if (rc) return rc;
@@ -419,6 +433,7 @@ extern "C" int vecchia_backward(const vecchia_view* view, const vecchia_kernel* 
                                 void* v_bar_out, double* theta_bar, void* scratch, size_t scratch_bytes,
                                 void* stream) {
     vecchia_clear_error();
+    TraceRange trace_range("vecchia_backward");
     Layout lay;
     int rc = check_view(view, &lay, "vecchia_backward");
     if (rc) return rc;
@@ -487,6 +502,7 @@ extern "C" int vecchia_backward_x(const vecchia_view* view, const vecchia_kernel
                                   const void* v_bar, const void* xi_bar_in, double logdet_bar, double* x_bar,
                                   void* scratch, size_t scratch_bytes, void* stream) {
     vecchia_clear_error();
+    TraceRange trace_range("vecchia_backward_x");
     Layout lay;
     int rc = check_view(view, &lay, "vecchia_backward_x");
     if (rc) return rc;
@@ -557,6 +573,7 @@ extern "C" int vecchia_fused_workspace_bytes(int64_t n, int32_t k, int32_t n0, i
 extern "C" int vecchia_forward_fused(const vecchia_view* view, const vecchia_kernel* kern, const void* xi, void* v,
                                      double* logdet, void* stream) {
     vecchia_clear_error();
+    TraceRange trace_range("vecchia_forward_fused");
     FusedLayout lay;
     int rc = check_fused_view(view, &lay, "vecchia_forward_fused");
     if (rc) return rc;
@@ -648,6 +665,7 @@ extern "C" int vecchia_forward_jvp(const vecchia_view* view, const vecchia_kerne
                                    const void* xi_dot, double sigma_dot, double ell_dot, void* v_dot,
                                    double* logdet_dot, void* scratch, size_t scratch_bytes, void* stream) {
     vecchia_clear_error();
+    TraceRange trace_range("vecchia_forward_jvp");
     Layout lay;
     int rc = check_view(view, &lay, "vecchia_forward_jvp");
     if (rc) return rc;
