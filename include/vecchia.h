@@ -53,6 +53,7 @@ extern "C" {
 #define VECCHIA_EUNSUPPORTED -4   /* valid but not compiled (e.g. k > 64, n0 > 128) */
 #define VECCHIA_EHIP         -5   /* a HIP runtime call failed */
 #define VECCHIA_EBUDGET      -6   /* serving admission: request exceeds the HBM budget */
+#define VECCHIA_EIO          -7   /* a graph file could not be opened, read or written, or is damaged */
 
 #define VECCHIA_FP64 0
 #define VECCHIA_FP32 1
@@ -221,6 +222,31 @@ int graph_export_children(const vecchia_graph* g, int64_t* child_ptr, int32_t* c
 /* Host time spent in the phases of graph_build, seconds: tree, neighbours,
  * depth, storage order.  times has 4 entries. */
 int graph_build_times(const vecchia_graph* g, double* times);
+
+/* Graph serialisation (host).  A built graph depends only on the points, k and
+ * n0 (Sec. 2.1 and 2.2: tree order, preceding k-NN, depth batches), so it can
+ * be written once and reused by later processes instead of being rebuilt.
+ *   graph_save  writes a finished graph to `path` (created or truncated): a
+ *               32-byte header (magic "VCGRAPH1", N int64, d, k, n0 int32,
+ *               one reserved int32), then the input coordinates (N x d
+ *               double, input order), the tree (slot -> input index, N int32;
+ *               split dimension per slot, N int32), the neighbour rows in
+ *               slot numbers ((N - n0) x k int32, ascending (distance, slot),
+ *               -1 padded) and the depth per slot (N int32), all
+ *               little-endian, and last the 64-bit FNV-1a hash of everything
+ *               before it.
+ *   graph_load  reads such a file into a new graph (*out, freed with
+ *               graph_free).  The hash and the sizes are checked first; the
+ *               content then goes through graph_build_begin_tree and
+ *               graph_build_finish_depth, so the tree, the rows and the
+ *               depths are checked as for a device build (a row is checked to
+ *               name preceding slots in ascending order, not re-searched).
+ *               n_threads as for graph_build.
+ * Errors: EINVAL (NULL argument, graph still pending, the content fails a
+ * check), EUNSUPPORTED (k above the compiled maximum), ENOMEM, EIO (open,
+ * read or write failed, wrong magic, truncated file, hash mismatch). */
+int graph_save(const vecchia_graph* g, const char* path);
+int graph_load(const char* path, int32_t n_threads, vecchia_graph** out);
 
 void graph_free(vecchia_graph* g);
 

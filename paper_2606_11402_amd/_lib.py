@@ -11,14 +11,14 @@ import threading
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libvecchia.so")
 
-OK, EINVAL, ENOMEM, ENOTPD, EUNSUPPORTED, EHIP, EBUDGET = 0, -1, -2, -3, -4, -5, -6
+OK, EINVAL, ENOMEM, ENOTPD, EUNSUPPORTED, EHIP, EBUDGET, EIO = 0, -1, -2, -3, -4, -5, -6, -7
 FP64, FP32 = 0, 1
 KMAX, N0MAX = 64, 128
 KNN_NODE_BYTES = 40
 EXP, M32, SE, M52, MATERN = 0, 1, 2, 3, 4
 
 _NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", ENOTPD: "ENOTPD", EUNSUPPORTED: "EUNSUPPORTED",
-          EHIP: "EHIP", EBUDGET: "EBUDGET"}
+          EHIP: "EHIP", EBUDGET: "EBUDGET", EIO: "EIO"}
 
 c_int32, c_int64, c_double, c_size_t, c_void_p = (ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
                                                  ctypes.c_size_t, ctypes.c_void_p)
@@ -71,6 +71,8 @@ _SIGNATURES = {
     "graph_export_points": (c_int32, [c_void_p, c_int32, c_void_p]),
     "graph_export_children": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "graph_build_times": (c_int32, [c_void_p, P(c_double)]),
+    "graph_save": (c_int32, [c_void_p, ctypes.c_char_p]),
+    "graph_load": (c_int32, [ctypes.c_char_p, c_int32, P(c_void_p)]),
     "graph_free": (None, [c_void_p]),
     "vecchia_workspace_bytes": (c_int32, [c_int64, c_int32, c_int32, c_int32, P(c_size_t)]),
     "vecchia_factor": (c_int32, [P(ViewStruct), P(KernelStruct), c_void_p]),

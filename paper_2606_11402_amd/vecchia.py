@@ -7,6 +7,7 @@ on the current torch stream.  Every array the library sees is a caller-owned
 tensor; the library allocates nothing on the device.
 """
 import ctypes
+import os
 from dataclasses import dataclass
 
 import numpy as np
@@ -145,6 +146,10 @@ class Graph:
                                   "device_search": ts[2] - ts[1],
                                   "device_depth": ts[3] - ts[2], "rows_to_host": ts[4] - ts[3],
                                   "finish": ts[5] - ts[4]}
+        self._adopt()
+
+    def _adopt(self):
+        """Read the sizes and storage maps of the native graph self._h."""
         n, d, kk, kp, nn0, nl = (ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(),
                                  ctypes.c_int32(), ctypes.c_int32())
         _lib.check(self._lib.graph_info(self._h, ctypes.byref(n), ctypes.byref(d), ctypes.byref(kk),
@@ -157,6 +162,24 @@ class Graph:
         self.level_ptr = np.empty(self.n_levels + 2, np.int32)
         _lib.check(self._lib.graph_export(self._h, _ptr(self.order), _ptr(self.slot), _ptr(self.level_ptr),
                                           _ptr(self.depth)), "graph_export")
+
+    def save(self, path):
+        """Write the graph to ``path`` (graph_save): the points, tree, rows
+        and depths, enough to rebuild it without the neighbour search."""
+        _lib.check(self._lib.graph_save(self._h, os.fsencode(path)), "graph_save")
+
+    @classmethod
+    def load(cls, path, n_threads=0):
+        """A graph read from a file written by ``save`` (graph_load); it is
+        checked as a device build is and equals the saved graph bit for bit."""
+        g = cls.__new__(cls)
+        g._lib = _lib.load()
+        handle = ctypes.c_void_p()
+        _lib.check(g._lib.graph_load(os.fsencode(path), int(n_threads), ctypes.byref(handle)), "graph_load")
+        g._h = handle
+        g.knn_seconds = g.tree_seconds = g.depth_sweeps = g.split_seconds = None
+        g._adopt()
+        return g
 
     def __del__(self):
         h = getattr(self, "_h", None)
