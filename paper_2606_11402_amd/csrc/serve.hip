@@ -137,7 +137,8 @@ struct Request {
     // graph products
     int n_levels = 0;
     std::vector<int32_t> order, level_ptr;
-    float* h_x = nullptr;          // pinned staging (GPU mode)
+    void* h_block = nullptr;       // one page-locked allocation holding the six staging arrays (GPU mode)
+    float* h_x = nullptr;          // pinned staging, carved from h_block
     int32_t* h_nbr = nullptr;
     float* h_in = nullptr;
     float* h_out = nullptr;
@@ -156,12 +157,8 @@ struct Request {
 };
 
 void free_pinned(Request& r) {
-    if (r.h_x) (void)hipHostFree(r.h_x);
-    if (r.h_nbr) (void)hipHostFree(r.h_nbr);
-    if (r.h_in) (void)hipHostFree(r.h_in);
-    if (r.h_out) (void)hipHostFree(r.h_out);
-    if (r.h_ld) (void)hipHostFree(r.h_ld);
-    if (r.h_lp) (void)hipHostFree(r.h_lp);
+    if (r.h_block) (void)hipHostFree(r.h_block);
+    r.h_block = nullptr;
     r.h_lp = nullptr;
     r.h_x = nullptr;
     r.h_nbr = nullptr;
@@ -312,13 +309,24 @@ void build_request(vecchia_server* s, Request* r, int wid) {
         r->fp = footprint(r->n, r->kp, r->n0, r->n_levels);
         const int64_t tiles = std::max<int64_t>((r->n - r->n0 + 63) / 64, 1);
         if (!s->mock) {
-            hipError_t e = hipHostMalloc((void**)&r->h_x, (size_t)r->n * 3 * sizeof(float), hipHostMallocDefault);
-            if (e == hipSuccess) e = hipHostMalloc((void**)&r->h_nbr, (size_t)tiles * r->kp * 64 * sizeof(int32_t), hipHostMallocDefault);
-            if (e == hipSuccess) e = hipHostMalloc((void**)&r->h_in, (size_t)r->n * sizeof(float), hipHostMallocDefault);
-            if (e == hipSuccess) e = hipHostMalloc((void**)&r->h_out, (size_t)r->n * sizeof(float), hipHostMallocDefault);
-            if (e == hipSuccess) e = hipHostMalloc((void**)&r->h_ld, sizeof(double), hipHostMallocDefault);
-            if (e == hipSuccess)
-                e = hipHostMalloc((void**)&r->h_lp, (size_t)(r->n_levels + 2) * sizeof(int32_t), hipHostMallocDefault);
+            // one page-locked block per request (a page-locking call costs far
+            // more than carving), each array at a 256-byte boundary
+            auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+            const size_t bx = up((size_t)r->n * 3 * sizeof(float)), bn = up((size_t)tiles * r->kp * 64 * sizeof(int32_t));
+            const size_t bv = up((size_t)r->n * sizeof(float)), bd = up(sizeof(double));
+            const size_t bl = up((size_t)(r->n_levels + 2) * sizeof(int32_t));
+            hipError_t e = hipHostMalloc(&r->h_block, bx + bn + 2 * bv + bd + bl, hipHostMallocDefault);
+            if (e == hipSuccess) {
+                char* base = static_cast<char*>(r->h_block);
+                r->h_x = reinterpret_cast<float*>(base);
+                r->h_nbr = reinterpret_cast<int32_t*>(base + bx);
+                r->h_in = reinterpret_cast<float*>(base + bx + bn);
+                r->h_out = reinterpret_cast<float*>(base + bx + bn + bv);
+                r->h_ld = reinterpret_cast<double*>(base + bx + bn + 2 * bv);
+                r->h_lp = reinterpret_cast<int32_t*>(base + bx + bn + 2 * bv + bd);
+            } else {
+                r->h_block = nullptr;
+            }
             if (e != hipSuccess) {
                 rc = VECCHIA_ENOMEM;
                 r->error = std::string("pinned staging: ") + hipGetErrorString(e);
