@@ -393,24 +393,55 @@ void build_depth(vecchia_graph& g, int nthreads) {
 void build_storage(vecchia_graph& g) {
     const int64_t n = g.n;
     const int L = g.n_levels;
-    std::vector<int64_t> count(L + 2, 0);
-    for (int64_t t = g.n0; t < n; ++t) count[g.depth[t]]++;
-    g.level_ptr.assign(L + 2, 0);
+    const int W = L + 2;
+    // The sparse slots, taken in the in-order sequence, are sorted stably by
+    // depth.  Counting sort over fixed chunks of the sequence: each chunk
+    // counts its slots per depth, an exclusive prefix over (depth, chunk)
+    // gives each chunk its first position in every batch, and the chunks then
+    // place their slots independently -- the same order as one serial pass.
+    const int nc = (int)std::max<int64_t>(1, std::min<int64_t>(g.nthreads, (n + (1 << 16) - 1) >> 16));
+    const int64_t chunk = (n + nc - 1) / nc;
+    std::vector<int64_t> cnt((size_t)nc * W, 0);
+    parallel_for(nc, 1, nc, [&](int64_t a, int64_t b) {
+        for (int64_t c = a; c < b; ++c) {
+            int64_t* my = &cnt[(size_t)c * W];
+            for (int64_t r = c * chunk; r < std::min(n, (c + 1) * chunk); ++r) {
+                const int64_t t = g.seq[r];
+                if (t >= g.n0) my[g.depth[t]]++;
+            }
+        }
+    });
+    g.level_ptr.assign(W, 0);
     g.level_ptr[1] = g.n0;
-    for (int l = 1; l <= L; ++l) g.level_ptr[l + 1] = (int32_t)(g.level_ptr[l] + count[l]);
-    std::vector<int64_t> fill(L + 2);
-    for (int l = 1; l <= L; ++l) fill[l] = g.level_ptr[l];
+    for (int l = 1; l <= L; ++l) {
+        int64_t off = g.level_ptr[l];
+        for (int c = 0; c < nc; ++c) {
+            const int64_t m = cnt[(size_t)c * W + l];
+            cnt[(size_t)c * W + l] = off;
+            off += m;
+        }
+        g.level_ptr[l + 1] = (int32_t)off;
+    }
     g.order.assign(n, -1);
     g.pos.assign(n, -1);
     for (int64_t t = 0; t < g.n0; ++t) g.order[t] = (int32_t)t;
     // inside a batch: in-order sequence of the tree (spatially coherent)
-    for (int64_t r = 0; r < n; ++r) {
-        const int64_t t = g.seq[r];
-        if (t >= g.n0) g.order[fill[g.depth[t]]++] = (int32_t)t;
-    }
-    for (int64_t s = 0; s < n; ++s) g.pos[g.order[s]] = (int32_t)s;
+    parallel_for(nc, 1, nc, [&](int64_t a, int64_t b) {
+        for (int64_t c = a; c < b; ++c) {
+            int64_t* fill = &cnt[(size_t)c * W];
+            for (int64_t r = c * chunk; r < std::min(n, (c + 1) * chunk); ++r) {
+                const int64_t t = g.seq[r];
+                if (t >= g.n0) g.order[fill[g.depth[t]]++] = (int32_t)t;
+            }
+        }
+    });
+    parallel_for(n, 1 << 16, g.nthreads, [&](int64_t a, int64_t b) {
+        for (int64_t s = a; s < b; ++s) g.pos[g.order[s]] = (int32_t)s;
+    });
     g.pos_r.resize(n);
-    for (int64_t r = 0; r < n; ++r) g.pos_r[r] = g.pos[g.seq[r]];
+    parallel_for(n, 1 << 16, g.nthreads, [&](int64_t a, int64_t b) {
+        for (int64_t r = a; r < b; ++r) g.pos_r[r] = g.pos[g.seq[r]];
+    });
 }
 
 // Row of sparse point sp in the device order: storage positions ascending,

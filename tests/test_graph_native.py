@@ -305,3 +305,17 @@ def test_begin_from_given_tree_rejects_other_trees():
         h = ctypes.c_void_p()
         assert lib.graph_build_begin_tree(xp, 900, 3, 8, 16, 2, ctypes.c_void_p(p.ctypes.data),
                                           ctypes.c_void_p(s.ctypes.data), ctypes.byref(h)) == _lib.EINVAL
+
+
+def test_thread_count_does_not_change_the_graph():
+    """The threaded phases (neighbour search, depths, the chunked counting
+    sort of the storage order) give the graph of the one-thread build."""
+    x = np.random.default_rng(21).random((150001, 3))
+    g1 = Graph(x, 8, 64, n_threads=1)
+    g4 = Graph(x, 8, 64, n_threads=4)
+    for name in ("order", "slot", "depth", "level_ptr"):
+        assert (getattr(g1, name) == getattr(g4, name)).all(), name
+    assert (g1.nbr(1) == g4.nbr(1)).all()
+    p1, c1 = g1.children()
+    p4, c4 = g4.children()
+    assert (p1 == p4).all() and (c1 == c4).all()
