@@ -254,24 +254,38 @@ struct QNode {
     int32_t sdim;
 };
 
+// In-order sequence of the tree.  The subtree sizes follow from N alone (a
+// node's left subtree holds floor(m/2) of the m points under it, the right
+// one the rest but the node), so the subtree of slot t covers the in-order
+// ranks [lo_t, lo_t + m_t), the node itself has rank lo_t + floor(m_t/2),
+// and the ranges of its children follow; one parallel pass per tree level,
+// root first.
 void inorder(vecchia_graph& g) {
     const int64_t n = g.n;
     g.seq.resize(n);
     g.rank_of.resize(n);
-    std::vector<int64_t> stack;
-    stack.reserve(128);
-    int64_t t = 0, r = 0;
-    while (t < n || !stack.empty()) {
-        while (t < n) {
-            stack.push_back(t);
-            t = left_child(t);
-        }
-        t = stack.back();
-        stack.pop_back();
-        g.seq[r] = (int32_t)t;
-        g.rank_of[t] = (int32_t)r;
-        ++r;
-        t = right_child(t);
+    std::vector<int32_t> lo(n), cnt(n);
+    lo[0] = 0;
+    cnt[0] = (int32_t)n;
+    const int levels = tree_level(n - 1) + 1;
+    for (int l = 0; l < levels; ++l) {
+        const int64_t first = (int64_t(1) << l) - 1, last = std::min<int64_t>(n, (int64_t(2) << l) - 1);
+        parallel_for(last - first, 1 << 15, g.nthreads, [&](int64_t a, int64_t b) {
+            for (int64_t t = first + a; t < first + b; ++t) {
+                const int64_t s = lo[t], m = cnt[t], h = m / 2;
+                g.seq[s + h] = (int32_t)t;
+                g.rank_of[t] = (int32_t)(s + h);
+                const int64_t lc = left_child(t), rc = right_child(t);
+                if (lc < n) {
+                    lo[lc] = (int32_t)s;
+                    cnt[lc] = (int32_t)h;
+                }
+                if (rc < n) {
+                    lo[rc] = (int32_t)(s + h + 1);
+                    cnt[rc] = (int32_t)(m - 1 - h);
+                }
+            }
+        });
     }
 }
 

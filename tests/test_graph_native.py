@@ -319,3 +319,19 @@ def test_thread_count_does_not_change_the_graph():
     p1, c1 = g1.children()
     p4, c4 = g4.children()
     assert (p1 == p4).all() and (c1 == c4).all()
+
+
+@pytest.mark.parametrize("n,n_threads", [(1000, 1), (70001, 4), (262147, 8)])
+def test_batches_follow_the_in_order_sequence(n, n_threads):
+    """In one dimension the tree is a binary search tree on (coordinate,
+    input index), so its in-order sequence is the sorted order: inside every
+    batch the storage order must ascend by that key (Sec. 2.2, batch
+    construction; the in-order layout inside a batch)."""
+    rng = np.random.default_rng(n)
+    x = np.round(rng.random(n), 3)                 # many ties
+    g = Graph(x, 4, 32, n_threads=n_threads)
+    for lev in range(1, g.n_levels + 1):
+        a, b = g.level_ptr[lev], g.level_ptr[lev + 1]
+        idx = g.order[a:b].astype(np.int64)
+        key = np.lexsort((idx, x[idx]))
+        assert (key == np.arange(b - a)).all(), lev
