@@ -208,7 +208,8 @@ int graph_export(const vecchia_graph* g, int32_t* order, int32_t* slot, int32_t*
 int graph_export_nbr(const vecchia_graph* g, int32_t layout, int32_t* nbr);
 
 /* Coordinates in storage order, 3 per point (zero padded for d < 3), as
- * double (precision VECCHIA_FP64) or float (VECCHIA_FP32): host, N x 3. */
+ * double (precision VECCHIA_FP64) or float (VECCHIA_FP32): host, N x 3.
+ * EINVAL for a NULL argument, a bad precision or a pending graph. */
 int graph_export_points(const vecchia_graph* g, int32_t precision, void* xs);
 
 /* Children lists for the reverse sweep of the adjoint (host): for storage

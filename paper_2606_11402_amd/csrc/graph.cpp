@@ -806,12 +806,14 @@ extern "C" int graph_export(const vecchia_graph* g, int32_t* order, int32_t* slo
                             int32_t* depth) {
     if (g && g->pending) return vecchia_set_error(VECCHIA_EINVAL, "graph_export: the graph is pending (graph_build_finish)");
     if (!g) return vecchia_set_error(VECCHIA_EINVAL, "graph_export: graph is NULL");
-    for (int64_t s = 0; s < g->n; ++s) {
-        const int32_t t = g->order[s];
-        if (order) order[s] = g->tree_perm[t];
-        if (slot) slot[s] = t;
-        if (depth) depth[s] = g->depth[t];
-    }
+    parallel_for(g->n, 1 << 16, g->nthreads, [&](int64_t a, int64_t b) {
+        for (int64_t s = a; s < b; ++s) {
+            const int32_t t = g->order[s];
+            if (order) order[s] = g->tree_perm[t];
+            if (slot) slot[s] = t;
+            if (depth) depth[s] = g->depth[t];
+        }
+    });
     if (level_ptr) std::memcpy(level_ptr, g->level_ptr.data(), sizeof(int32_t) * g->level_ptr.size());
     return VECCHIA_OK;
 }
@@ -823,11 +825,13 @@ extern "C" int graph_export_nbr(const vecchia_graph* g, int32_t layout, int32_t*
     const int64_t ns = g->n - g->n0;
     const int k = g->k, kp = g->kp;
     if (layout == 0) {
-        for (int64_t sp = 0; sp < ns; ++sp) {
-            const int32_t t = g->order[g->n0 + sp];
-            const int32_t* row = &g->nbr[(size_t)(t - g->n0) * k];
-            for (int m = 0; m < k; ++m) nbr[sp * k + m] = row[m] >= 0 ? g->pos_r[row[m]] : -1;
-        }
+        parallel_for(ns, 1 << 14, g->nthreads, [&](int64_t a, int64_t b) {
+            for (int64_t sp = a; sp < b; ++sp) {
+                const int32_t t = g->order[g->n0 + sp];
+                const int32_t* row = &g->nbr[(size_t)(t - g->n0) * k];
+                for (int m = 0; m < k; ++m) nbr[sp * k + m] = row[m] >= 0 ? g->pos_r[row[m]] : -1;
+            }
+        });
         return VECCHIA_OK;
     }
     const int64_t tiles = (ns + 63) / 64;
@@ -844,18 +848,21 @@ extern "C" int graph_export_nbr(const vecchia_graph* g, int32_t layout, int32_t*
 }
 
 extern "C" int graph_export_points(const vecchia_graph* g, int32_t precision, void* xs) {
+    if (g && g->pending) return vecchia_set_error(VECCHIA_EINVAL, "graph_export_points: the graph is pending (graph_build_finish)");
     if (!g || !xs) return vecchia_set_error(VECCHIA_EINVAL, "graph_export_points: NULL argument");
     if (precision != VECCHIA_FP64 && precision != VECCHIA_FP32)
         return vecchia_set_error(VECCHIA_EINVAL, "graph_export_points: bad precision %d", precision);
-    for (int64_t s = 0; s < g->n; ++s) {
-        const double* p = &g->xs[(size_t)g->order[s] * 3];
-        for (int c = 0; c < 3; ++c) {
-            if (precision == VECCHIA_FP64)
-                static_cast<double*>(xs)[s * 3 + c] = p[c];
-            else
-                static_cast<float*>(xs)[s * 3 + c] = (float)p[c];
+    parallel_for(g->n, 1 << 16, g->nthreads, [&](int64_t a, int64_t b) {
+        for (int64_t s = a; s < b; ++s) {
+            const double* p = &g->xs[(size_t)g->order[s] * 3];
+            for (int c = 0; c < 3; ++c) {
+                if (precision == VECCHIA_FP64)
+                    static_cast<double*>(xs)[s * 3 + c] = p[c];
+                else
+                    static_cast<float*>(xs)[s * 3 + c] = (float)p[c];
+            }
         }
-    }
+    });
     return VECCHIA_OK;
 }
 

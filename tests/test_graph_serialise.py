@@ -163,4 +163,6 @@ def test_pending_graph_not_saved(tmp_path):
     _lib.check(lib.graph_build_begin(x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 100, 3, 4, 8, 1,
                                      ctypes.byref(h)), "graph_build_begin")
     assert lib.graph_save(h, str(tmp_path / "p.graph").encode()) == _lib.EINVAL
+    out = np.empty((100, 3))
+    assert lib.graph_export_points(h, _lib.FP64, ctypes.c_void_p(out.ctypes.data)) == _lib.EINVAL
     lib.graph_free(h)
