@@ -4,7 +4,8 @@
 // and, separately, with ThreadSanitizer; any report fails the run.
 //
 // Scenarios: graph builds with every dimension and several widths and thread
-// counts, including a padded dense-check row set; the scheduler with requests
+// counts, including a padded dense-check row set, each saved to a graph file,
+// loaded back and compared, and loaded again cut short; the scheduler with requests
 // that complete, a request cancelled while it waits for memory, one cancelled
 // while its graph is still being built, and both released at once after the
 // cancel (the path that must not leave a queue pointing at freed memory).
@@ -15,6 +16,8 @@
 #include <random>
 #include <thread>
 #include <vector>
+
+#include <unistd.h>
 
 #include "vecchia.h"
 
@@ -76,6 +79,27 @@ static void graphs() {
         CHECK(graph_export_children(g, cptr.data(), child.data()) == VECCHIA_OK);
         CHECK(cptr[n] <= ns * k);
         for (int64_t s = 0; s < ns * k; ++s) CHECK(rows[s] < n0 + s / k);   // neighbours precede
+        // graph file round trip, then the same file cut short
+        char path[] = "/tmp/vecchia_graph_XXXXXX";
+        const int fd = mkstemp(path);
+        CHECK(fd >= 0);
+        close(fd);
+        CHECK(graph_save(g, path) == VECCHIA_OK);
+        vecchia_graph* h = nullptr;
+        CHECK(graph_load(path, c.threads, &h) == VECCHIA_OK);
+        std::vector<int32_t> order2(n), rows2(rows.size());
+        CHECK(graph_export(h, order2.data(), nullptr, nullptr, nullptr) == VECCHIA_OK);
+        CHECK(graph_export_nbr(h, 0, rows2.data()) == VECCHIA_OK);
+        CHECK(order2 == order && std::equal(rows2.begin(), rows2.begin() + ns * k, rows.begin()));
+        graph_free(h);
+        FILE* f = std::fopen(path, "r+b");
+        CHECK(f && std::fseek(f, 0, SEEK_END) == 0);
+        const long len = std::ftell(f);
+        std::fclose(f);
+        CHECK(truncate(path, len / 2) == 0);
+        h = nullptr;
+        CHECK(graph_load(path, c.threads, &h) == VECCHIA_EIO && h == nullptr);
+        std::remove(path);
         graph_free(g);
     }
 }

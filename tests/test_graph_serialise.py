@@ -116,6 +116,12 @@ def test_damaged_files_refused(saved, tmp_path):
     bad.write_bytes(bytes(_rehash(hdr)))
     _expect(bad, _lib.EIO)
     _expect(tmp_path / "missing.graph", _lib.EIO)
+    huge = bytearray(data[:HEADER])
+    huge[8:16] = ((1 << 31) - 1).to_bytes(8, "little")        # a header claiming 2^31 - 1 points
+    bad.write_bytes(bytes(huge))
+    with pytest.raises(VecchiaError) as e:                    # refused by its length, before any allocation
+        Graph.load(bad)
+    assert e.value.code == _lib.EIO and "header implies" in str(e.value)
 
 
 def test_wrong_content_refused(saved, tmp_path):

@@ -26,7 +26,7 @@ def _build(tmp, kind):
     san = ["address", "undefined"] if kind == "asan" else ["thread"]
     host_flags = ["-fsanitize=" + s for s in san]
     objs = []
-    for src in ("graph.cpp", "status.cpp"):
+    for src in ("graph.cpp", "graph_io.cpp", "status.cpp"):
         obj = os.path.join(tmp, src + ".o")
         subprocess.run([CLANG, "-c", os.path.join(CSRC, src), "-o", obj, "-ffp-contract=off"] + common + host_flags,
                        check=True)
