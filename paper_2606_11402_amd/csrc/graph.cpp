@@ -31,6 +31,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <memory>
 #include <new>
 #include <thread>
 #include <vector>
@@ -522,7 +523,10 @@ int64_t check_tree(const double* x, int64_t n, int d, const int32_t* perm, const
         int32_t id;
     };
     auto less = [](const Key& a, const Key& b) { return a.c < b.c || (a.c == b.c && a.id < b.id); };
-    std::vector<Key> lo((size_t)n * 3), hi((size_t)n * 3);
+    // not zeroed: an entry (slot, dimension < d) is written before any read of
+    // it, since slots are visited deepest level first and read only their
+    // children's entries
+    std::unique_ptr<Key[]> lo(new Key[(size_t)n * 3]), hi(new Key[(size_t)n * 3]);
     const int levels = tree_level(n - 1) + 1;
     for (int l = levels - 1; l >= 0; --l) {
         const int64_t first = (int64_t(1) << l) - 1, last = std::min<int64_t>(n, (int64_t(2) << l) - 1);
