@@ -857,21 +857,33 @@ extern "C" int graph_export_children(const vecchia_graph* g, int64_t* child_ptr,
     const int64_t ns = g->n - g->n0;
     if (ns * g->kp >= (int64_t(1) << 31))
         return vecchia_set_error(VECCHIA_EUNSUPPORTED, "graph_export_children: Ns*kp = %lld does not fit int32", (long long)(ns * g->kp));
+    // Counts and placement run in parallel with atomic per-list cursors, so
+    // the order inside a list depends on the threads; each list is sorted
+    // afterwards.  Its entries sp * kp + m are distinct and a row names a
+    // point at most once, so the sorted list is the list in row order.
     std::vector<int64_t> cnt(g->n + 1, 0);
-    for (int64_t sp = 0; sp < ns; ++sp) {
-        const int32_t t = g->order[g->n0 + sp];
-        const int32_t* row = &g->nbr[(size_t)(t - g->n0) * g->k];
-        for (int m = 0; m < g->k; ++m)
-            if (row[m] >= 0) cnt[g->pos_r[row[m]] + 1]++;
-    }
+    int64_t* c = cnt.data();
+    parallel_for(ns, 1 << 14, g->nthreads, [&](int64_t a, int64_t b) {
+        for (int64_t sp = a; sp < b; ++sp) {
+            const int32_t t = g->order[g->n0 + sp];
+            const int32_t* row = &g->nbr[(size_t)(t - g->n0) * g->k];
+            for (int m = 0; m < g->k; ++m)
+                if (row[m] >= 0) __atomic_fetch_add(&c[g->pos_r[row[m]] + 1], int64_t(1), __ATOMIC_RELAXED);
+        }
+    });
     for (int64_t j = 0; j < g->n; ++j) cnt[j + 1] += cnt[j];
     std::memcpy(child_ptr, cnt.data(), sizeof(int64_t) * (g->n + 1));
-    int32_t row[VECCHIA_KMAX];
-    for (int64_t sp = 0; sp < ns; ++sp) {
-        device_row(*g, sp, row);                       // m: position in the device row
-        for (int m = 0; m < g->k; ++m)
-            if (row[m] >= 0) child[cnt[row[m]]++] = (int32_t)(sp * g->kp + m);
-    }
+    parallel_for(ns, 1 << 14, g->nthreads, [&](int64_t a, int64_t b) {
+        int32_t row[VECCHIA_KMAX];
+        for (int64_t sp = a; sp < b; ++sp) {
+            device_row(*g, sp, row);                   // m: position in the device row
+            for (int m = 0; m < g->k; ++m)
+                if (row[m] >= 0) child[__atomic_fetch_add(&c[row[m]], int64_t(1), __ATOMIC_RELAXED)] = (int32_t)(sp * g->kp + m);
+        }
+    });
+    parallel_for(g->n, 1 << 14, g->nthreads, [&](int64_t a, int64_t b) {
+        for (int64_t j = a; j < b; ++j) std::sort(child + child_ptr[j], child + child_ptr[j + 1]);
+    });
     return VECCHIA_OK;
 }
 

@@ -105,6 +105,24 @@ def test_tiled_layout_matches_row_major():
     assert (tl.reshape(g.ntiles, g.kp, 64)[-1, :, g.ns % 64:] == -1).all()
 
 
+@pytest.mark.parametrize("n,k,n_threads", [(150001, 16, 8), (70000, 32, 3)])
+def test_children_lists_against_the_device_rows(n, k, n_threads):
+    """Children lists of a cloud large enough for the threaded export, against
+    the inversion of the device rows written out with NumPy: list j holds the
+    packed entries sp * kp + m with row sp naming j at position m, ascending."""
+    x = np.random.default_rng(n).random((n, 3))
+    g = Graph(x, k, 64, n_threads=n_threads)
+    ptr, child = g.children()
+    nb = g.nbr(1).reshape(g.ntiles, g.kp, 64).transpose(0, 2, 1).reshape(-1, g.kp)[:g.ns]
+    sp, m = np.nonzero(nb >= 0)
+    j = nb[sp, m].astype(np.int64)
+    entry = sp.astype(np.int64) * g.kp + m
+    key = np.lexsort((entry, j))
+    want_ptr = np.concatenate([[0], np.cumsum(np.bincount(j, minlength=g.n))])
+    assert (ptr == want_ptr).all()
+    assert (child[:ptr[-1]] == entry[key]).all()
+
+
 def test_children_lists_invert_neighbours():
     x = np.random.default_rng(9).random((800, 3))
     g = Graph(x, 8, 16)
