@@ -58,7 +58,8 @@ static std::vector<double> points(int64_t n, int d, unsigned seed) {
 static void graphs() {
     struct Case { int64_t n; int d, k, n0, threads; };
     const Case cases[] = {{3000, 3, 8, 128, 1}, {5000, 3, 32, 64, 4}, {2000, 2, 16, 32, 2},
-                          {1500, 1, 5, 16, 3},  {65, 3, 32, 1, 2},   {300, 3, 8, 300, 1}};
+                          {1500, 1, 5, 16, 3},  {65, 3, 32, 1, 2},   {300, 3, 8, 300, 1},
+                          {40000, 3, 8, 64, 4}};   // last: several chunks per threaded pass
     for (const Case& c : cases) {
         std::vector<double> x = points(c.n, c.d, (unsigned)(c.n + c.k));
         vecchia_graph* g = nullptr;
